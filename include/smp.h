@@ -1,0 +1,208 @@
+/*
+ * smp.h - C-ABI of the SMP-PCA hot path for AMD Instinct MI355X (gfx950).
+ *
+ * SMP-PCA (Wu, Bhojanapalli, Sanghavi, Dimakis, "Single Pass PCA of Matrix
+ * Products", arXiv 1610.06656) computes a rank-r approximation U V^T of A^T B
+ * for A (d x n1) and B (d x n2) while reading A and B only once (Alg. 1):
+ *
+ *   1. one pass: Gaussian JL sketches A~ = Pi A, B~ = Pi B with Pi(c,l) ~ N(0,1/k),
+ *      and the exact column norms ||A_i||, ||B_j||           (Alg. 1 step 2)
+ *   2. sample each (i,j) independently with probability q^_ij = min(1, q_ij),
+ *      q_ij = m (||A_i||^2/(2 n2 ||A||_F^2) + ||B_j||^2/(2 n1 ||B||_F^2))
+ *                                                         (Eq. (1), Alg. 1 step 3)
+ *   3. rescaled-JL estimates M~_ij = ||A_i|| ||B_j|| <A~_i,B~_j>/(||A~_i|| ||B~_j||)
+ *      on the sampled set Omega only                     (Eq. (2), Alg. 1 step 4)
+ *   4. WAltMin: weighted alternating least squares with weights w_ij = 1/q^_ij,
+ *      initialised by the top-r SVD of w .* P_Omega(M~) and a row trim
+ *                                                  (Alg. 1 step 5; Appendix A, Alg. 2)
+ *
+ * Conventions for every call below:
+ *  - All matrix/vector pointers are DEVICE pointers on the context's device,
+ *    allocated and owned by the caller, unless stated otherwise. The library
+ *    never frees caller memory.
+ *  - All work is enqueued asynchronously on the context's HIP stream, in call
+ *    order. Calls that must return a data-dependent size to the host
+ *    (smp_sample) synchronise that stream once.
+ *  - Layouts: A is d x n1 row-major with leading dimension lda >= n1
+ *    (element (l,i) at A[l*lda + i]), the layout of a contiguous (d, n1) torch
+ *    tensor; B likewise. Sketches are stored TRANSPOSED, At (n1 x k) row-major
+ *    with At[i*k + c] = A~(c,i), so that each column's sketch A~_i is
+ *    contiguous. U (n1 x r) and V (n2 x r) are row-major FP64.
+ *  - Arguments are validated before anything is launched; on an error the
+ *    outputs are untouched and smp_last_error(ctx) describes the problem.
+ *    Device faults surface as SMP_ERR_DEVICE.
+ *  - A context is used by one host thread at a time.
+ *
+ * Random streams: every random draw comes from Philox4x32-10 (Salmon et al.,
+ * SC'11) keyed by params.seed. Call (col_block, row, tag) uses the counter
+ * (col_block, row mod 2^32, tag, row >> 32) and key (seed mod 2^32, seed >> 32),
+ * and serves the four columns 4*col_block..4*col_block+3 of `row`.
+ *   Pi(c,l) = Z/sqrt(k), Z = Box-Muller lane (c mod 4) of call (c/4, l, tag 1),
+ *     lanes (0,1) from words (w0,w1), lanes (2,3) from (w2,w3), with
+ *     u = ((a>>8)+1) 2^-24, phi = (b>>8) 2^-24, Z = sqrt(-2 ln u)(cos 2 pi phi, sin 2 pi phi);
+ *   coin(i,j) = word (j mod 4) of call (j/4, i, tag 2);
+ *   subset(i,j) (SPLIT mode) = (word (j mod 4) of call (j/4, i, tag 3) * (2T+1)) >> 32.
+ */
+#ifndef SMP_H_
+#define SMP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum smp_status {
+  SMP_OK = 0,
+  SMP_ERR_INVALID_ARG = 1,  /* a size, pointer or parameter is out of range */
+  SMP_ERR_OUT_OF_MEMORY = 2,/* a device allocation of library workspace failed */
+  SMP_ERR_DEVICE = 3,       /* a HIP runtime call or kernel failed */
+  SMP_ERR_NUMERIC = 4,      /* non-finite input or factorisation failure */
+  SMP_ERR_CAPACITY = 5,     /* caller buffer too small; the required size is reported */
+  SMP_ERR_STATE = 6         /* call out of order (e.g. push after end) */
+} smp_status;
+
+typedef enum smp_precision {
+  SMP_PREC_FP32 = 0,        /* sketch GEMM operands FP32 (v_mfma_f32_16x16x4_f32) */
+  SMP_PREC_BF16 = 1         /* operands rounded to BF16, FP32 accumulate */
+} smp_precision;
+
+typedef enum smp_omega_mode {
+  SMP_OMEGA_REUSE = 0,      /* every WAltMin half-step uses all of Omega */
+  SMP_OMEGA_SPLIT = 1       /* Alg. 2 step 3: 2T+1 random subsets, one per step */
+} smp_omega_mode;
+
+enum { SMP_B_IS_A = 1u };   /* flags: B is A (PCA of A^T A, Section 3 Remark 3) */
+
+/* The problem statement of Section 2 (A, B, r, k, m, T) plus the seed. */
+typedef struct smp_params {
+  int64_t d, n1, n2;  /* A is d x n1, B is d x n2 */
+  int32_t k;          /* sketch size, Pi is k x d; 1 <= k <= 4096 */
+  int32_t r;          /* target rank; 1 <= r <= min(n1, n2, 32) */
+  int32_t T;          /* WAltMin iterations; 0 <= T <= 1000 */
+  int32_t prec;       /* smp_precision of the sketch GEMM */
+  int32_t omega_mode; /* smp_omega_mode */
+  uint32_t flags;     /* SMP_B_IS_A */
+  double m;           /* sample-count parameter of Eq. (1); > 0 */
+  uint64_t seed;      /* Philox key */
+  int32_t init_iters; /* subspace iterations of the WAltMin init; 0 = default (12) */
+  int32_t reserved;   /* must be 0 */
+} smp_params;
+
+typedef struct smp_ctx smp_ctx;
+
+/* Sampled entry set Omega (Alg. 1 step 3) with weights and estimates, as two
+ * sorted listings: CSR (by row i, then column j) and CSC (by column j, then
+ * row i). All arrays are caller-owned device buffers of the stated lengths;
+ * the per-entry arrays hold `cap` elements. smp_sample fills the index and
+ * weight arrays and `nnz`; smp_estimate fills mt_csr and mt_csc. sub_csr and
+ * sub_csc may be NULL in REUSE mode. */
+typedef struct smp_omega {
+  int64_t n1, n2;     /* grid size */
+  int64_t cap;        /* capacity of every per-entry array */
+  int64_t nnz;        /* |Omega|, written by smp_sample (host value) */
+  int64_t *row_ptr;   /* n1+1 CSR offsets */
+  int32_t *col_idx;   /* cap: CSR column of each entry */
+  double *w_csr;      /* cap: w = 1/q^ (Alg. 2 step 2) */
+  double *mt_csr;     /* cap: M~ on the entry (Eq. (2)) */
+  uint8_t *sub_csr;   /* cap: subset id in [0, 2T] (SPLIT mode) or NULL */
+  int64_t *col_ptr;   /* n2+1 CSC offsets */
+  int32_t *row_idx;   /* cap: CSC row of each entry */
+  double *w_csc;      /* cap */
+  double *mt_csc;     /* cap */
+  uint8_t *sub_csc;   /* cap or NULL */
+} smp_omega;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a
+ * hipStream_t; NULL = the default stream). The context owns its workspace. */
+smp_status smp_create(smp_ctx **ctx, int device, void *hip_stream);
+void smp_destroy(smp_ctx *ctx);
+const char *smp_status_str(smp_status s);
+const char *smp_last_error(const smp_ctx *ctx);
+smp_status smp_set_stream(smp_ctx *ctx, void *hip_stream);
+
+/* Validate params (the checks listed with smp_params). */
+smp_status smp_check_params(const smp_params *p);
+
+/* Device bytes of library workspace that smp_solve needs for `p`, excluding
+ * the caller's inputs and outputs. The Omega part uses the expected size
+ * m plus a 6-sigma margin. */
+smp_status smp_workspace_size(const smp_params *p, size_t *bytes);
+
+/* ---- a1: the sketching matrix Pi (Alg. 1 step 2) ----------------------------
+ * Writes rows l0 .. l0+nrows-1 of Pi^T: out[(l-l0)*k + c] = Pi(c, l) (FP32,
+ * N(0,1/k), the same values the sketch pass uses). For inspection and tests;
+ * the sketch pass itself never stores Pi. */
+smp_status smp_pi_fill(smp_ctx *ctx, const smp_params *p, int64_t l0, int64_t nrows, float *out);
+
+/* ---- a2+a3: the single pass (Alg. 1 step 2; Section 2 "Step 1") -------------
+ * At = (Pi A)^T (n1 x k), Bt = (Pi B)^T (n2 x k), na2[i] = ||A_i||^2 (n1),
+ * nb2[j] = ||B_j||^2 (n2), all FP32. With SMP_B_IS_A, B/ldb are ignored and Bt,
+ * nb2 receive copies of At, na2 (they may also be NULL). Squared norms use
+ * compensated FP32 sums per lane and an FP64 combine. */
+smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                      int64_t ldb, float *At, float *Bt, float *na2, float *nb2);
+
+/* Streaming form of the same pass: rows may be pushed in any order and any
+ * block sizes (each row exactly once). The state holds O(k (n1+n2)) partial
+ * sums; rows row0 .. row0+nrows-1 of A are A_rows[0 .. nrows-1] (leading
+ * dimension lda). smp_sketch_end writes the same outputs as smp_sketch and
+ * frees nothing; smp_sketch_free releases the state. */
+typedef struct smp_sketch_state smp_sketch_state;
+smp_status smp_sketch_begin(smp_ctx *ctx, const smp_params *p, smp_sketch_state **st);
+smp_status smp_sketch_push(smp_ctx *ctx, smp_sketch_state *st, const float *A_rows, int64_t lda,
+                           const float *B_rows, int64_t ldb, int64_t row0, int64_t nrows);
+smp_status smp_sketch_end(smp_ctx *ctx, smp_sketch_state *st, float *At, float *Bt, float *na2, float *nb2);
+void smp_sketch_free(smp_sketch_state *st);
+
+/* ---- a4: sampling (Eq. (1); Alg. 1 step 3; Alg. 2 steps 2-3) ---------------
+ * From the FP32 squared norms na2 (n1) and nb2 (n2), draws Omega and writes
+ * both listings and the weights into `om` (om->n1, n2, cap and the pointers
+ * set by the caller). q^ is evaluated in FP64 in a fixed order (F_A summed
+ * sequentially in blocks of 256, then over the blocks; den = (2 n2) F_A;
+ * alpha_i = na2_i/den; q = m (alpha_i + beta_j); q^ = min(1,q)); (i,j) is kept
+ * iff coin(i,j) < floor(q^ 2^32). Synchronises the stream once. If |Omega| >
+ * cap, returns SMP_ERR_CAPACITY with om->nnz = |Omega| and no entries written. */
+smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const float *nb2, smp_omega *om);
+
+/* ---- a3 (rescale) + a5: estimates on Omega (Eq. (2)) -------------------------
+ * Fills om->mt_csr and om->mt_csc from the transposed sketches At (n1 x k),
+ * Bt (n2 x k) and the squared norms. cos is clamped to [-1,1]; M~ = 0 when any
+ * of the four norms is 0. */
+smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt,
+                        const float *na2, const float *nb2, smp_omega *om);
+
+/* ---- a6-a8: WAltMin (Appendix A, Alg. 2) and the canonical output -----------
+ * Init: top-r left/right singular subspace of R = w .* P_Omega0(M~) by block
+ * subspace iteration; rows of U0 with ||U0_i|| > 8 sqrt(r) sqrt(na2_i / F_A)
+ * are zeroed (trim). T alternating steps: V_j = argmin sum_i w_ij (q_i^T v - M~_ij)^2
+ * with q the orthonormalised U, then the same for U against the orthonormalised
+ * V; every r x r system is solved by FP64 Cholesky (pivot <= 1e-12 max diag:
+ * retry on G + 1e-9 tr(G)/r I; else 0). Output in canonical form
+ * U V^T -> U diag(sigma) V^T with U (n1 x r), V (n2 x r) orthonormal and
+ * sigma (r, descending; may be NULL, then sigma is folded into U). */
+smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, const float *na2, double *U,
+                       double *V, double *sigma);
+
+/* ---- stage timing ------------------------------------------------------------
+ * With timing enabled, smp_solve (and smp_sketch) record HIP events on the
+ * context's stream around each stage; smp_stage_times writes the durations (ms)
+ * of the last call: [0] sketch kernel, [1] sketch reduction, [2] sampling,
+ * [3] estimate, [4] WAltMin (init + iterations + canonical form). Stages that
+ * did not run report 0. n is the capacity of ms (up to 5 are written).
+ * Enabling costs one event pair per stage; it does not synchronise more. */
+smp_status smp_set_timing(smp_ctx *ctx, int enable);
+smp_status smp_stage_times(smp_ctx *ctx, float *ms, int n);
+
+/* ---- the whole of Alg. 1 -----------------------------------------------------
+ * smp_sketch -> smp_sample -> smp_estimate -> smp_waltmin with library-owned
+ * intermediates. Outputs as smp_waltmin. B may equal A (or SMP_B_IS_A). */
+smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
+                     double *U, double *V, double *sigma);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMP_H_ */

@@ -1,0 +1,223 @@
+"""Python binding of libsmp (include/smp.h): the same entry points, taking torch
+tensors for device memory and torch streams for ordering. Argument marshalling
+only: every step of the method runs in the HIP kernels behind the C-ABI.
+"""
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from ._lib import SmpOmega, SmpParams
+
+
+class SmpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_status_name(status)} ({status}): {msg}")
+        self.status = status
+
+
+def _status_name(s):
+    lib = _lib.load()
+    return lib.smp_status_str(s).decode()
+
+
+def _ptr(t, dtype=None, name="tensor", dense=True):
+    """Device address of a tensor; dense buffers must be contiguous (A and B
+    only need unit column stride and pass dense=False)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if dense and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not dense and t.dim() == 2 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_m(n1, n2, r):
+    """4 n r ln n with n = max(n1, n2)."""
+    n = max(n1, n2)
+    return 4.0 * n * r * math.log(n)
+
+
+def make_params(d, n1, n2, k, r, T=10, m=None, seed=161006656, prec=_lib.SMP_PREC_FP32,
+                omega_mode=_lib.SMP_OMEGA_REUSE, b_is_a=False, init_iters=0):
+    p = SmpParams()
+    p.d, p.n1, p.n2 = int(d), int(n1), int(n2)
+    p.k, p.r, p.T = int(k), int(r), int(T)
+    p.prec, p.omega_mode = int(prec), int(omega_mode)
+    p.flags = _lib.SMP_B_IS_A if b_is_a else 0
+    p.m = float(default_m(n1, n2, r) if m is None else m)
+    p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    p.init_iters = int(init_iters)
+    p.reserved = 0
+    return p
+
+
+def smp_check_params(p):
+    lib = _lib.load()
+    s = lib.smp_check_params(ctypes.byref(p))
+    if s != _lib.SMP_OK:
+        raise SmpError(s, lib.smp_last_error(None).decode())
+
+
+def smp_workspace_size(p):
+    lib = _lib.load()
+    out = ctypes.c_size_t(0)
+    s = lib.smp_workspace_size(ctypes.byref(p), ctypes.byref(out))
+    if s != _lib.SMP_OK:
+        raise SmpError(s, lib.smp_last_error(None).decode())
+    return out.value
+
+
+class Omega:
+    """Caller-owned device arrays of the sampled set (the smp_omega struct)."""
+
+    def __init__(self, n1, n2, cap, device, split=False):
+        self.n1, self.n2, self.cap = n1, n2, cap
+        kw = dict(device=device)
+        self.row_ptr = torch.zeros(n1 + 1, dtype=torch.int64, **kw)
+        self.col_ptr = torch.zeros(n2 + 1, dtype=torch.int64, **kw)
+        c = max(cap, 1)
+        self.col_idx = torch.zeros(c, dtype=torch.int32, **kw)
+        self.row_idx = torch.zeros(c, dtype=torch.int32, **kw)
+        self.w_csr = torch.zeros(c, dtype=torch.float64, **kw)
+        self.w_csc = torch.zeros(c, dtype=torch.float64, **kw)
+        self.mt_csr = torch.zeros(c, dtype=torch.float64, **kw)
+        self.mt_csc = torch.zeros(c, dtype=torch.float64, **kw)
+        self.sub_csr = torch.zeros(c, dtype=torch.uint8, **kw) if split else None
+        self.sub_csc = torch.zeros(c, dtype=torch.uint8, **kw) if split else None
+        self.nnz = 0
+
+    def struct(self):
+        o = SmpOmega()
+        o.n1, o.n2, o.cap, o.nnz = self.n1, self.n2, self.cap, self.nnz
+        for name in ("row_ptr", "col_idx", "w_csr", "mt_csr", "sub_csr",
+                     "col_ptr", "row_idx", "w_csc", "mt_csc", "sub_csc"):
+            t = getattr(self, name)
+            setattr(o, name, t.data_ptr() if t is not None else None)
+        return o
+
+
+class Context:
+    """An smp_ctx bound to a device and a torch stream (the current stream by default)."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = _lib.load()
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.device = dev
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = st
+        h = ctypes.c_void_p()
+        s = self.lib.smp_create(ctypes.byref(h), dev.index or 0, ctypes.c_void_p(st.cuda_stream))
+        if s != _lib.SMP_OK:
+            raise SmpError(s, self.lib.smp_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.smp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s):
+        if s != _lib.SMP_OK:
+            raise SmpError(s, self.lib.smp_last_error(self.h).decode())
+
+    # ---- entry points (same names as the C-ABI)
+    def smp_pi_fill(self, p, l0, nrows, out):
+        self._check(self.lib.smp_pi_fill(self.h, ctypes.byref(p), int(l0), int(nrows),
+                                         _ptr(out, torch.float32, "out")))
+
+    def smp_sketch(self, p, A, B, At, Bt, na2, nb2):
+        lda = A.stride(0)
+        ldb = B.stride(0) if B is not None else 0
+        if A.stride(1) != 1 or (B is not None and B.stride(1) != 1):
+            raise ValueError("A and B must have unit column stride")
+        self._check(self.lib.smp_sketch(self.h, ctypes.byref(p), _ptr(A, torch.float32, "A", dense=False), lda,
+                                        _ptr(B, torch.float32, "B", dense=False), ldb, _ptr(At, torch.float32, "At"),
+                                        _ptr(Bt, torch.float32, "Bt"), _ptr(na2, torch.float32, "na2"),
+                                        _ptr(nb2, torch.float32, "nb2")))
+
+    def smp_sketch_begin(self, p):
+        st = ctypes.c_void_p()
+        self._check(self.lib.smp_sketch_begin(self.h, ctypes.byref(p), ctypes.byref(st)))
+        return st
+
+    def smp_sketch_push(self, st, A_rows, B_rows, row0):
+        nrows = A_rows.shape[0]
+        ldb = B_rows.stride(0) if B_rows is not None else 0
+        self._check(self.lib.smp_sketch_push(self.h, st, _ptr(A_rows, torch.float32, "A_rows", dense=False), A_rows.stride(0),
+                                             _ptr(B_rows, torch.float32, "B_rows", dense=False), ldb, int(row0), int(nrows)))
+
+    def smp_sketch_end(self, st, At, Bt, na2, nb2):
+        self._check(self.lib.smp_sketch_end(self.h, st, _ptr(At, torch.float32, "At"), _ptr(Bt, torch.float32, "Bt"),
+                                            _ptr(na2, torch.float32, "na2"), _ptr(nb2, torch.float32, "nb2")))
+
+    def smp_sketch_free(self, st):
+        self.lib.smp_sketch_free(st)
+
+    def smp_sample(self, p, na2, nb2, om):
+        o = om.struct()
+        s = self.lib.smp_sample(self.h, ctypes.byref(p), _ptr(na2, torch.float32, "na2"),
+                                _ptr(nb2, torch.float32, "nb2"), ctypes.byref(o))
+        om.nnz = o.nnz
+        self._check(s)
+        return om.nnz
+
+    def smp_estimate(self, p, At, Bt, na2, nb2, om):
+        o = om.struct()
+        self._check(self.lib.smp_estimate(self.h, ctypes.byref(p), _ptr(At, torch.float32, "At"),
+                                          _ptr(Bt, torch.float32, "Bt"), _ptr(na2, torch.float32, "na2"),
+                                          _ptr(nb2, torch.float32, "nb2"), ctypes.byref(o)))
+
+    def smp_waltmin(self, p, om, na2, U, V, sigma=None):
+        o = om.struct()
+        self._check(self.lib.smp_waltmin(self.h, ctypes.byref(p), ctypes.byref(o), _ptr(na2, torch.float32, "na2"),
+                                         _ptr(U, torch.float64, "U"), _ptr(V, torch.float64, "V"),
+                                         _ptr(sigma, torch.float64, "sigma")))
+
+    def smp_set_timing(self, enable=True):
+        self._check(self.lib.smp_set_timing(self.h, 1 if enable else 0))
+
+    def smp_stage_times(self):
+        """ms of the last call's stages: sketch kernel, sketch reduction,
+        sampling, estimate, WAltMin."""
+        arr = (ctypes.c_float * 5)()
+        self._check(self.lib.smp_stage_times(self.h, arr, 5))
+        return dict(zip(("sketch", "sketch_finish", "sample", "estimate", "waltmin"), list(arr)))
+
+    def smp_solve(self, p, A, B, U, V, sigma=None):
+        if A.stride(1) != 1 or (B is not None and B.stride(1) != 1):
+            raise ValueError("A and B must have unit column stride")
+        Bp = B if B is not None else A
+        self._check(self.lib.smp_solve(self.h, ctypes.byref(p), _ptr(A, torch.float32, "A", dense=False), A.stride(0),
+                                       _ptr(Bp, torch.float32, "B", dense=False), Bp.stride(0), _ptr(U, torch.float64, "U"),
+                                       _ptr(V, torch.float64, "V"), _ptr(sigma, torch.float64, "sigma")))
+
+
+def solve(A, B, k, r, T=10, m=None, seed=161006656, prec=_lib.SMP_PREC_FP32, omega_mode=_lib.SMP_OMEGA_REUSE,
+          ctx=None, init_iters=0):
+    """Alg. 1 on device tensors A (d x n1), B (d x n2, or None for A = B).
+    Returns (U, sigma, V): U diag(sigma) V^T approximates A^T B."""
+    d, n1 = A.shape
+    n2 = n1 if B is None else B.shape[1]
+    p = make_params(d, n1, n2, k, r, T, m, seed, prec, omega_mode, b_is_a=B is None, init_iters=init_iters)
+    ctx = ctx or Context(A.device)
+    U = torch.empty(n1, r, dtype=torch.float64, device=A.device)
+    V = torch.empty(n2, r, dtype=torch.float64, device=A.device)
+    s = torch.empty(r, dtype=torch.float64, device=A.device)
+    ctx.smp_solve(p, A, B, U, V, s)
+    return U, s, V

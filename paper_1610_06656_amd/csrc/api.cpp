@@ -1,0 +1,501 @@
+// C-ABI of the SMP-PCA hot path (declared in include/smp.h): argument
+// validation, library workspace, and the stage orchestration of Alg. 1
+// (sketch -> sample -> estimate -> WAltMin) on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "smp_internal.hpp"
+
+using smp::SketchPlan;
+
+namespace {
+
+constexpr int kMaxK = 4096;
+constexpr int kMaxR = 32;
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+thread_local std::string g_err_no_ctx;
+
+smp_status fail(smp_ctx *ctx, smp_status s, const std::string &msg) {
+  if (ctx) ctx->last_error = msg;
+  else g_err_no_ctx = msg;
+  return s;
+}
+
+smp_status hip_fail(smp_ctx *ctx, hipError_t e, const char *where) {
+  return fail(ctx, SMP_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define SMP_HIP(ctx, expr)                                   \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
+  } while (0)
+
+std::string check(const smp_params *p) {
+  if (!p) return "params is NULL";
+  if (p->d < 1 || p->n1 < 1 || p->n2 < 1) return "d, n1, n2 must be >= 1";
+  if (p->k < 1 || p->k > kMaxK) return "k must be in [1, 4096]";
+  if (p->r < 1 || p->r > kMaxR || p->r > p->n1 || p->r > p->n2) return "r must be in [1, min(n1, n2, 32)]";
+  if (p->T < 0 || p->T > 1000) return "T must be in [0, 1000]";
+  if (p->T > 127 && p->omega_mode == SMP_OMEGA_SPLIT) return "SPLIT mode needs 2T+1 <= 255 subsets";
+  if (!(p->m > 0.0) || !std::isfinite(p->m)) return "m must be a finite positive number";
+  if (p->prec != SMP_PREC_FP32) return "precision not available (only SMP_PREC_FP32)";
+  if (p->omega_mode != SMP_OMEGA_REUSE && p->omega_mode != SMP_OMEGA_SPLIT) return "unknown omega_mode";
+  if (p->init_iters < 0 || p->init_iters > 1000) return "init_iters must be in [0, 1000]";
+  if (p->reserved != 0) return "reserved must be 0";
+  if ((p->flags & SMP_B_IS_A) && p->n1 != p->n2) return "SMP_B_IS_A needs n1 == n2";
+  if ((p->n1 + 1) * 4 > INT32_MAX || p->n2 > INT32_MAX / 4) return "n1, n2 too large for int32 entry indices";
+  return "";
+}
+
+// Number of d-splits of the sketch pass: enough workgroups to fill the chip
+// (about two per CU) with at least 256 rows per split.
+int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
+  const int64_t tiles = (n1 + pl.ncol_tile - 1) / pl.ncol_tile + (n2 + pl.ncol_tile - 1) / pl.ncol_tile;
+  const int64_t per = (int64_t)pl.kt * tiles;
+  int64_t S = (512 + per - 1) / per;
+  S = std::min<int64_t>(S, std::max<int64_t>(1, d / 256));
+  S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
+  return (int)S;
+}
+
+smp_status ensure(smp_ctx *ctx, Buf &b, size_t bytes) {
+  if (b.bytes >= bytes) return SMP_OK;
+  if (b.p) {
+    hipStreamSynchronize(ctx->stream);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) return SMP_OK;
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return SMP_OK;
+}
+
+size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+enum Stage { kStSketch = 0, kStFinish = 1, kStSample = 2, kStEstimate = 3, kStWaltmin = 4 };
+
+void mark(smp_ctx *ctx, Stage s, bool end) {
+  if (!ctx->timing) return;
+  hipEventRecord(ctx->events[2 * s + (end ? 1 : 0)], ctx->stream);
+  if (end) ctx->recorded[s] = true;
+}
+
+template <typename T>
+T *take(char *&c, size_t count) {
+  T *o = reinterpret_cast<T *>(c);
+  c += al(count * sizeof(T));
+  return o;
+}
+
+}  // namespace
+
+struct smp_sketch_state {
+  smp_ctx *ctx;
+  smp_params p;
+  SketchPlan plan;
+  int S;
+  float *part;
+  double *npart;
+  bool ended;
+};
+
+struct smp_ctx_bufs {
+  Buf sketch, samplews, head, omega, est, wm;
+};
+
+namespace {
+smp_ctx_bufs &bufs(smp_ctx *ctx);
+}
+
+extern "C" {
+
+const char *smp_status_str(smp_status s) {
+  switch (s) {
+    case SMP_OK: return "ok";
+    case SMP_ERR_INVALID_ARG: return "invalid argument";
+    case SMP_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case SMP_ERR_DEVICE: return "device error";
+    case SMP_ERR_NUMERIC: return "numeric error";
+    case SMP_ERR_CAPACITY: return "buffer capacity exceeded";
+    case SMP_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char *smp_last_error(const smp_ctx *ctx) { return ctx ? ctx->last_error.c_str() : g_err_no_ctx.c_str(); }
+
+smp_status smp_check_params(const smp_params *p) {
+  const std::string m = check(p);
+  if (!m.empty()) return fail(nullptr, SMP_ERR_INVALID_ARG, m);
+  return SMP_OK;
+}
+
+smp_status smp_create(smp_ctx **ctx, int device, void *hip_stream) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return fail(nullptr, SMP_ERR_INVALID_ARG, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, SMP_ERR_DEVICE, "hipSetDevice failed");
+  smp_ctx *c = new (std::nothrow) smp_ctx();
+  if (!c) return fail(nullptr, SMP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipHostMalloc((void **)&c->host_pinned, 8 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(nullptr, SMP_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
+  }
+  c->ws = new smp_ctx_bufs();
+  *ctx = c;
+  return SMP_OK;
+}
+
+void smp_destroy(smp_ctx *ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
+  if (b) {
+    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm})
+      if (x->p) hipFree(x->p);
+    delete b;
+  }
+  if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
+  for (hipEvent_t &e : ctx->events)
+    if (e) hipEventDestroy(e);
+  delete ctx;
+}
+
+smp_status smp_set_stream(smp_ctx *ctx, void *hip_stream) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return SMP_OK;
+}
+
+smp_status smp_set_timing(smp_ctx *ctx, int enable) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  if (enable && !ctx->events[0])
+    for (hipEvent_t &e : ctx->events) SMP_HIP(ctx, hipEventCreate(&e));
+  ctx->timing = enable != 0;
+  return SMP_OK;
+}
+
+smp_status smp_stage_times(smp_ctx *ctx, float *ms, int n) {
+  if (!ctx || !ms || n < 0) return fail(ctx, SMP_ERR_INVALID_ARG, "ctx or ms is NULL");
+  for (int s = 0; s < 5 && s < n; ++s) {
+    ms[s] = 0.0f;
+    if (ctx->timing && ctx->recorded[s]) {
+      SMP_HIP(ctx, hipEventSynchronize(ctx->events[2 * s + 1]));
+      SMP_HIP(ctx, hipEventElapsedTime(&ms[s], ctx->events[2 * s], ctx->events[2 * s + 1]));
+    }
+  }
+  return SMP_OK;
+}
+
+smp_status smp_workspace_size(const smp_params *p, size_t *bytes) {
+  const std::string m = check(p);
+  if (!m.empty()) return fail(nullptr, SMP_ERR_INVALID_ARG, m);
+  if (!bytes) return fail(nullptr, SMP_ERR_INVALID_ARG, "bytes is NULL");
+  const SketchPlan pl = smp::sketch_plan(p->k);
+  const int S = choose_splits(pl, p->d, p->n1, p->n2);
+  const int64_t nt = p->n1 + p->n2, k = p->k;
+  size_t s = 0;
+  s += al((size_t)S * nt * pl.kpad * 4) + al((size_t)S * nt * 8);        // sketch partials
+  s += al(nt * k * 4) + al(nt * 4);                                       // sketches + norms
+  s += al(64) + al(nt * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);   // sampling
+  const double nnz = std::min<double>((double)p->n1 * (double)p->n2, p->m + 6.0 * std::sqrt(p->m) + 64.0);
+  s += 2 * al((size_t)(p->n1 + p->n2 + 2) * 8) + (size_t)(nnz * (4 + 8 + 8 + 1) * 2) + 8 * 256;  // omega
+  s += 2 * al(nt * 8);                                                    // estimate
+  s += smp::waltmin_ws_bytes(p->n1, p->n2, p->r, (int64_t)nnz);
+  *bytes = s;
+  return SMP_OK;
+}
+
+smp_status smp_pi_fill(smp_ctx *ctx, const smp_params *p, int64_t l0, int64_t nrows, float *out) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  if (l0 < 0 || nrows < 0 || l0 + nrows > p->d) return fail(ctx, SMP_ERR_INVALID_ARG, "rows out of [0, d)");
+  if (nrows > 0 && !out) return fail(ctx, SMP_ERR_INVALID_ARG, "out is NULL");
+  if (nrows == 0) return SMP_OK;
+  SMP_HIP(ctx, smp::pi_fill(l0, nrows, p->k, p->seed, out, ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_sketch_begin(smp_ctx *ctx, const smp_params *p, smp_sketch_state **st) {
+  if (!ctx || !st) return fail(ctx, SMP_ERR_INVALID_ARG, "ctx or st is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  auto *s = new (std::nothrow) smp_sketch_state();
+  if (!s) return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  s->ctx = ctx;
+  s->p = *p;
+  s->plan = smp::sketch_plan(p->k);
+  s->S = choose_splits(s->plan, p->d, p->n1, p->n2);
+  const int64_t n2 = (p->flags & SMP_B_IS_A) ? 0 : p->n2;
+  const int64_t nt = p->n1 + n2;
+  const size_t pb = (size_t)s->S * nt * s->plan.kpad * sizeof(float);
+  const size_t nb = (size_t)s->S * nt * sizeof(double);
+  if (hipMalloc((void **)&s->part, pb) != hipSuccess || hipMalloc((void **)&s->npart, nb) != hipSuccess) {
+    hipGetLastError();
+    if (s->part) hipFree(s->part);
+    delete s;
+    return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "sketch state allocation failed");
+  }
+  SMP_HIP(ctx, hipMemsetAsync(s->part, 0, pb, ctx->stream));
+  SMP_HIP(ctx, hipMemsetAsync(s->npart, 0, nb, ctx->stream));
+  s->ended = false;
+  *st = s;
+  return SMP_OK;
+}
+
+smp_status smp_sketch_push(smp_ctx *ctx, smp_sketch_state *st, const float *A_rows, int64_t lda, const float *B_rows,
+                           int64_t ldb, int64_t row0, int64_t nrows) {
+  if (!ctx || !st) return fail(ctx, SMP_ERR_INVALID_ARG, "ctx or st is NULL");
+  if (st->ended) return fail(ctx, SMP_ERR_STATE, "push after end");
+  const smp_params &p = st->p;
+  const bool same = (p.flags & SMP_B_IS_A) != 0;
+  if (row0 < 0 || nrows < 0 || row0 + nrows > p.d) return fail(ctx, SMP_ERR_INVALID_ARG, "rows out of [0, d)");
+  if (nrows == 0) return SMP_OK;
+  if (!A_rows || lda < p.n1) return fail(ctx, SMP_ERR_INVALID_ARG, "A is NULL or lda < n1");
+  if (!same && (!B_rows || ldb < p.n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
+  SMP_HIP(ctx, smp::sketch_push(st->plan, A_rows, lda, p.n1, same ? nullptr : B_rows, ldb, same ? 0 : p.n2, row0,
+                                nrows, p.k, p.seed, st->S, st->part, st->npart, ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_sketch_end(smp_ctx *ctx, smp_sketch_state *st, float *At, float *Bt, float *na2, float *nb2) {
+  if (!ctx || !st) return fail(ctx, SMP_ERR_INVALID_ARG, "ctx or st is NULL");
+  const smp_params &p = st->p;
+  const bool same = (p.flags & SMP_B_IS_A) != 0;
+  if (!At || !na2) return fail(ctx, SMP_ERR_INVALID_ARG, "At or na2 is NULL");
+  if (!same && (!Bt || !nb2)) return fail(ctx, SMP_ERR_INVALID_ARG, "Bt or nb2 is NULL");
+  const int64_t n2 = same ? 0 : p.n2;
+  SMP_HIP(ctx, smp::sketch_finish(st->plan, st->part, st->npart, st->S, p.n1, n2, p.k, At, same ? nullptr : Bt, na2,
+                                  same ? nullptr : nb2, ctx->stream));
+  if (same) {
+    if (Bt && Bt != At)
+      SMP_HIP(ctx, hipMemcpyAsync(Bt, At, (size_t)p.n1 * p.k * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    if (nb2 && nb2 != na2)
+      SMP_HIP(ctx, hipMemcpyAsync(nb2, na2, (size_t)p.n1 * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  st->ended = true;
+  return SMP_OK;
+}
+
+void smp_sketch_free(smp_sketch_state *st) {
+  if (!st) return;
+  hipStreamSynchronize(st->ctx->stream);
+  hipFree(st->part);
+  hipFree(st->npart);
+  delete st;
+}
+
+smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
+                      float *At, float *Bt, float *na2, float *nb2) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  const bool same = (p->flags & SMP_B_IS_A) != 0;
+  if (!A || lda < p->n1) return fail(ctx, SMP_ERR_INVALID_ARG, "A is NULL or lda < n1");
+  if (!same && (!B || ldb < p->n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
+  if (!At || !na2 || (!same && (!Bt || !nb2))) return fail(ctx, SMP_ERR_INVALID_ARG, "output pointer is NULL");
+  // the one-shot pass keeps its partials in the context's workspace
+  const SketchPlan pl = smp::sketch_plan(p->k);
+  const int S = choose_splits(pl, p->d, p->n1, p->n2);
+  const int64_t n2 = same ? 0 : p->n2;
+  const int64_t nt = p->n1 + n2;
+  const size_t pb = al((size_t)S * nt * pl.kpad * 4), nb = al((size_t)S * nt * 8);
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.sketch, pb + nb);
+  if (s != SMP_OK) return s;
+  float *part = static_cast<float *>(b.sketch.p);
+  double *npart = reinterpret_cast<double *>(static_cast<char *>(b.sketch.p) + pb);
+  for (bool &r : ctx->recorded) r = false;
+  SMP_HIP(ctx, hipMemsetAsync(b.sketch.p, 0, pb + nb, ctx->stream));
+  mark(ctx, kStSketch, false);
+  SMP_HIP(ctx, smp::sketch_push(pl, A, lda, p->n1, same ? nullptr : B, ldb, n2, 0, p->d, p->k, p->seed, S, part,
+                                npart, ctx->stream));
+  mark(ctx, kStSketch, true);
+  mark(ctx, kStFinish, false);
+  SMP_HIP(ctx, smp::sketch_finish(pl, part, npart, S, p->n1, n2, p->k, At, same ? nullptr : Bt, na2,
+                                  same ? nullptr : nb2, ctx->stream));
+  mark(ctx, kStFinish, true);
+  if (same) {
+    if (Bt && Bt != At)
+      SMP_HIP(ctx, hipMemcpyAsync(Bt, At, (size_t)p->n1 * p->k * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    if (nb2 && nb2 != na2)
+      SMP_HIP(ctx, hipMemcpyAsync(nb2, na2, (size_t)p->n1 * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return SMP_OK;
+}
+
+smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const float *nb2, smp_omega *om) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  if (!na2 || !nb2 || !om) return fail(ctx, SMP_ERR_INVALID_ARG, "na2, nb2 or om is NULL");
+  if (om->n1 != p->n1 || om->n2 != p->n2) return fail(ctx, SMP_ERR_INVALID_ARG, "om grid differs from params");
+  if (!om->row_ptr || !om->col_ptr || (om->cap > 0 && (!om->col_idx || !om->w_csr || !om->row_idx || !om->w_csc)))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "om index or weight array is NULL");
+  const bool split = p->omega_mode == SMP_OMEGA_SPLIT;
+  if (split && om->cap > 0 && (!om->sub_csr || !om->sub_csc))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "SPLIT mode needs sub_csr and sub_csc");
+  const int64_t n1 = p->n1, n2 = p->n2, nt = n1 + n2;
+  smp_ctx_bufs &b = bufs(ctx);
+  const size_t need = al(64) + al(n1 * 8) + al(n2 * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);
+  smp_status s = ensure(ctx, b.samplews, need);
+  if (s != SMP_OK) return s;
+  char *c = static_cast<char *>(b.samplews.p);
+  smp::SampleWs ws;
+  ws.stats = take<double>(c, 8);
+  ws.alpha = take<double>(c, n1);
+  ws.beta = take<double>(c, n2);
+  ws.blocks = take<double>(c, nt / 256 + 4);
+  ws.cnt = take<int64_t>(c, nt + 2);
+  SMP_HIP(ctx, smp::sample_prepare(na2, nb2, n1, n2, ws, ctx->stream));
+  SMP_HIP(ctx, smp::sample_count(ws, n1, n2, p->m, p->seed, om->row_ptr, om->col_ptr, ws.cnt, ctx->stream));
+  SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, om->row_ptr + n1, 8, hipMemcpyDeviceToHost, ctx->stream));
+  SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned + 1, om->col_ptr + n2, 8, hipMemcpyDeviceToHost, ctx->stream));
+  SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int64_t nnz = ctx->host_pinned[0];
+  if (nnz != ctx->host_pinned[1]) return fail(ctx, SMP_ERR_DEVICE, "row and column listings disagree on |Omega|");
+  om->nnz = nnz;
+  if (nnz > om->cap)
+    return fail(ctx, SMP_ERR_CAPACITY, "|Omega| = " + std::to_string(nnz) + " exceeds cap " + std::to_string(om->cap));
+  SMP_HIP(ctx, smp::sample_fill(ws, n1, n2, p->m, p->seed, p->T, split ? 1 : 0, *om, ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt, const float *na2,
+                        const float *nb2, smp_omega *om) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  if (!At || !Bt || !na2 || !nb2 || !om) return fail(ctx, SMP_ERR_INVALID_ARG, "input pointer is NULL");
+  if (om->n1 != p->n1 || om->n2 != p->n2) return fail(ctx, SMP_ERR_INVALID_ARG, "om grid differs from params");
+  if (om->nnz > 0 && (!om->mt_csr || !om->mt_csc)) return fail(ctx, SMP_ERR_INVALID_ARG, "mt arrays are NULL");
+  const int64_t n1 = p->n1, n2 = p->n2;
+  const bool same = At == Bt && na2 == nb2;
+  smp_ctx_bufs &b = bufs(ctx);
+  const size_t need = 2 * al(n1 * 8) + 2 * al(n2 * 8);
+  smp_status s = ensure(ctx, b.est, need);
+  if (s != SMP_OK) return s;
+  char *c = static_cast<char *>(b.est.p);
+  double *na = take<double>(c, n1);
+  double *nb = take<double>(c, n2);
+  double *sa = take<double>(c, n1);
+  double *sb = take<double>(c, n2);
+  if (same) {
+    nb = na;
+    sb = sa;
+  }
+  SMP_HIP(ctx, smp::estimate_run(At, Bt, na2, nb2, n1, n2, p->k, na, nb, sa, sb, *om, ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, const float *na2, double *U, double *V,
+                       double *sigma) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  if (!om || !na2 || !U || !V) return fail(ctx, SMP_ERR_INVALID_ARG, "input or output pointer is NULL");
+  if (om->n1 != p->n1 || om->n2 != p->n2) return fail(ctx, SMP_ERR_INVALID_ARG, "om grid differs from params");
+  if (p->omega_mode == SMP_OMEGA_SPLIT && om->nnz > 0 && (!om->sub_csr || !om->sub_csc))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "SPLIT mode needs sub_csr and sub_csc");
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.wm, smp::waltmin_ws_bytes(p->n1, p->n2, p->r, om->nnz));
+  if (s != SMP_OK) return s;
+  SMP_HIP(ctx, smp::waltmin_run(*p, *om, na2, U, V, sigma, b.wm.p, ctx->stream, nullptr));
+  return SMP_OK;
+}
+
+smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
+                     double *U, double *V, double *sigma) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string msg = check(p);
+  if (!msg.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, msg);
+  smp_params q = *p;
+  if (B == A && p->n1 == p->n2 && ldb == lda) q.flags |= SMP_B_IS_A;
+  const bool same = (q.flags & SMP_B_IS_A) != 0;
+  if (!A || lda < q.n1 || (!same && (!B || ldb < q.n2)))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "A/B is NULL or leading dimension too small");
+  if (!U || !V) return fail(ctx, SMP_ERR_INVALID_ARG, "U or V is NULL");
+  const int64_t n1 = q.n1, n2 = q.n2, k = q.k;
+  smp_ctx_bufs &b = bufs(ctx);
+
+  // sketches, norms and the listing offsets; the entry arrays are sized after counting
+  const size_t head = al(n1 * k * 4) + al(n2 * k * 4) + al(n1 * 4) + al(n2 * 4) + al((n1 + 2) * 8) + al((n2 + 2) * 8);
+  smp_status s = ensure(ctx, b.head, head);
+  if (s != SMP_OK) return s;
+  char *hc = static_cast<char *>(b.head.p);
+  float *At = take<float>(hc, n1 * k);
+  float *Bt = take<float>(hc, n2 * k);
+  float *na2 = take<float>(hc, n1);
+  float *nb2 = take<float>(hc, n2);
+  int64_t *rp = take<int64_t>(hc, n1 + 2);
+  int64_t *cp = take<int64_t>(hc, n2 + 2);
+  s = smp_sketch(ctx, &q, A, lda, B, ldb, At, Bt, na2, nb2);
+  if (s != SMP_OK) return s;
+
+  // Omega: count first (one readback), then size the entry arrays exactly
+  smp_omega om{};
+  om.n1 = n1;
+  om.n2 = n2;
+  om.cap = 0;
+  om.row_ptr = rp;
+  om.col_ptr = cp;
+  mark(ctx, kStSample, false);
+  s = smp_sample(ctx, &q, na2, nb2, &om);
+  if (s != SMP_OK && s != SMP_ERR_CAPACITY) return s;
+  const int64_t nnz = om.nnz;
+  const bool split = q.omega_mode == SMP_OMEGA_SPLIT;
+  const size_t ent = 2 * (al(nnz * 4) + al(nnz * 8) + al(nnz * 8) + (split ? al(nnz) : 0));
+  s = ensure(ctx, b.omega, std::max<size_t>(ent, 256));
+  if (s != SMP_OK) return s;
+  char *c = static_cast<char *>(b.omega.p);
+  om.cap = nnz;
+  om.col_idx = take<int32_t>(c, nnz);
+  om.w_csr = take<double>(c, nnz);
+  om.mt_csr = take<double>(c, nnz);
+  om.row_idx = take<int32_t>(c, nnz);
+  om.w_csc = take<double>(c, nnz);
+  om.mt_csc = take<double>(c, nnz);
+  om.sub_csr = split ? take<uint8_t>(c, nnz) : nullptr;
+  om.sub_csc = split ? take<uint8_t>(c, nnz) : nullptr;
+  s = smp_sample(ctx, &q, na2, nb2, &om);
+  if (s != SMP_OK) return s;
+  mark(ctx, kStSample, true);
+  mark(ctx, kStEstimate, false);
+  s = smp_estimate(ctx, &q, At, same ? At : Bt, na2, same ? na2 : nb2, &om);
+  if (s != SMP_OK) return s;
+  mark(ctx, kStEstimate, true);
+  mark(ctx, kStWaltmin, false);
+  s = smp_waltmin(ctx, &q, &om, na2, U, V, sigma);
+  if (s != SMP_OK) return s;
+  mark(ctx, kStWaltmin, true);
+  SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return SMP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+smp_ctx_bufs &bufs(smp_ctx *ctx) { return *static_cast<smp_ctx_bufs *>(ctx->ws); }
+}  // namespace

@@ -1,0 +1,78 @@
+// Host-side internals shared by the C-ABI implementation files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/smp.h"
+
+struct smp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  // growable library workspace (device), reused across calls
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  // small pinned host buffer for the few readbacks
+  int64_t *host_pinned = nullptr;
+  // stage timing: events[2*s] / events[2*s+1] bracket stage s
+  bool timing = false;
+  hipEvent_t events[10] = {};
+  bool recorded[5] = {};
+};
+
+namespace smp {
+
+// ---- sketch --------------------------------------------------------------------
+struct SketchPlan {
+  int mt_total;   // ceil(k/16) m-tiles of 16 sketch rows
+  int kt;         // WG chunks along k
+  int mt;         // m-tiles per chunk
+  int nv;         // columns per lane (2 or 4): a wave covers 16*nv columns
+  int ncol_tile;  // columns per WG = 4 waves * 16 * nv
+  int kpad;       // mt_total * 16
+};
+
+SketchPlan sketch_plan(int k);
+
+// Pass over rows [row0, row0+rows) of A (and B). part: [S][n1+n2][kpad] FP32,
+// npart: [S][n1+n2] FP64; zeroed by the caller before the first push.
+hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
+                       int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, float *part,
+                       double *npart, hipStream_t st);
+
+// Reduce the S partials into At (n1 x k), Bt (n2 x k), na2, nb2 (Bt/nb2 may be null).
+hipError_t sketch_finish(const SketchPlan &pl, const float *part, const double *npart, int S, int64_t n1,
+                         int64_t n2, int k, float *At, float *Bt, float *na2, float *nb2, hipStream_t st);
+
+hipError_t pi_fill(int64_t l0, int64_t nrows, int k, uint64_t seed, float *out, hipStream_t st);
+
+// ---- sampling ------------------------------------------------------------------
+struct SampleWs {
+  double *stats;     // [4]: F_A, F_B, den_A, den_B
+  double *alpha;     // n1
+  double *beta;      // n2
+  double *blocks;    // max(n1, n2)/256 + 1
+  int64_t *cnt;      // max(n1, n2) + 1
+};
+hipError_t sample_prepare(const float *na2, const float *nb2, int64_t n1, int64_t n2, SampleWs &ws,
+                          hipStream_t st);
+hipError_t sample_count(const SampleWs &ws, int64_t n1, int64_t n2, double m, uint64_t seed, int64_t *row_ptr,
+                        int64_t *col_ptr, int64_t *scan_tmp, hipStream_t st);
+hipError_t sample_fill(const SampleWs &ws, int64_t n1, int64_t n2, double m, uint64_t seed, int T, int split,
+                       const smp_omega &om, hipStream_t st);
+
+// ---- estimate ------------------------------------------------------------------
+// na/nb: sketch-column norms, sa/sb: data-column norms (FP64 scratch, n1 / n2)
+hipError_t estimate_run(const float *At, const float *Bt, const float *na2, const float *nb2, int64_t n1,
+                        int64_t n2, int k, double *na, double *nb, double *sa, double *sb, const smp_omega &om,
+                        hipStream_t st);
+
+// ---- WAltMin -------------------------------------------------------------------
+size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t nnz);
+hipError_t waltmin_run(const smp_params &p, const smp_omega &om, const float *na2, double *U, double *V,
+                       double *sigma, void *ws, hipStream_t st, int *status_flag_host);
+
+}  // namespace smp

@@ -1,0 +1,654 @@
+// WAltMin (Appendix A, Alg. 2) in FP64 on the GPU, plus the canonical output form.
+//
+// Init (Alg. 2 steps 4-6): the top-r singular subspace of R = w .* P_Omega0(M~)
+// by block subspace iteration (Halko, Martinsson, Tropp 2011, Alg. 4.4) on a
+// block of p = r + 10 columns: Y <- orth(R^T orth(R Y)), then a Rayleigh-Ritz
+// step on R Y gives U0, S0, V0; rows of U0 with ||U0_i|| > 8 sqrt(r) ||A_i||/||A||_F
+// are zeroed (the trim of step 6, with the row-norm bound the paper states
+// for the trimmed initial iterate in the proof of its initialisation lemma).
+//
+// Iterations (Alg. 2 steps 7-10): each half-step is one weighted least-squares
+// problem per output row, min_v sum_e w_e (q_e^T v - M~_e)^2 over the row's
+// sampled entries, with q the rows of the orthonormalised fixed factor. The
+// normal equations G = sum w q q^T, h = sum w M~ q are accumulated on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64: four sampled entries per instruction,
+// operand A = w q^T, operand B = [q | M~]), copied to LDS, and solved there by
+// a right-looking Cholesky with the pivot rule: a pivot <= 1e-12 max diag(G)
+// fails, the factorisation is retried once on G + 1e-9 trace(G)/r I, and a row
+// that still fails or has no samples gets 0. One wave owns one row.
+//
+// Orthonormalisation is CholeskyQR2 (Fukaya et al. 2014): Gram X^T X (fixed
+// reduction order), LDS Cholesky, X <- X L^-T, twice. A pivot below 1e-13 of
+// the largest diagonal entry drops that direction (its column becomes 0).
+// Small symmetric eigenproblems use a parallel cyclic Jacobi method
+// (round-robin ordering, one wave).
+//
+// Canonical output: with V orthonormal, U V^T = P diag(sigma) (V W)^T where
+// U^T U = W diag(sigma^2) W^T and P = U W diag(1/sigma); each component's sign
+// makes the largest-magnitude entry of its V column positive.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "smp_device.hpp"
+#include "smp_internal.hpp"
+
+namespace smp {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+hipError_t fixed_total(const float *x, int64_t n, double *blocks, double *out, hipStream_t st);
+
+namespace {
+
+constexpr int kMaxP = 64;       // largest block width handled by the small kernels
+constexpr int kInitOversample = 10;
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)std::max<int64_t>(1, (a + b - 1) / b); }
+
+// ---------------------------------------------------------------- Gram
+// part[b][a*p + c] = sum over rows of block b of X[i][a] X[i][c]
+__global__ __launch_bounds__(256) void gram_partial_kernel(const double *__restrict__ X, int64_t n, int p,
+                                                           int64_t rows_per_block, double *__restrict__ part) {
+  __shared__ double rows[32 * kMaxP];
+  const int t = threadIdx.x;
+  const int pp = p * p;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  const int64_t r0 = blockIdx.x * rows_per_block;
+  const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_block);
+  for (int64_t base = r0; base < r1; base += 32) {
+    const int nr = (int)std::min<int64_t>(32, r1 - base);
+    for (int e = t; e < nr * p; e += 256) rows[e] = X[base * p + e];
+    __syncthreads();
+    for (int rr = 0; rr < nr; ++rr) {
+      const double *row = rows + rr * p;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int idx = t + 256 * u;
+        if (idx < pp) acc[u] = fma(row[idx / p], row[idx % p], acc[u]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = t + 256 * u;
+    if (idx < pp) part[(int64_t)blockIdx.x * pp + idx] = acc[u];
+  }
+}
+
+__global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, int p, double *__restrict__ G) {
+  const int pp = p * p;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < pp; idx += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * pp + idx];
+    G[idx] = s;
+  }
+}
+
+// ---------------------------------------------------------------- Cholesky -> L^-T
+// One wave. G (p x p) -> M = L^-T (upper triangular), X M has orthonormal
+// columns when X^T X = G. shift_rel > 0 adds shift_rel * trace/p to the diagonal.
+__global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__ G, int p, double shift_rel,
+                                                      double *__restrict__ M, double *__restrict__ Lout) {
+  __shared__ double L[kMaxP * kMaxP];
+  __shared__ double dinv[kMaxP];
+  const int t = threadIdx.x;
+  for (int e = t; e < p * p; e += 64) L[e] = G[e];
+  __syncthreads();
+  double tr = 0.0, mx = 0.0;
+  for (int a = 0; a < p; ++a) {
+    tr += L[a * p + a];
+    mx = fmax(mx, L[a * p + a]);
+  }
+  const double shift = shift_rel > 0.0 ? shift_rel * tr / p : 0.0;
+  __syncthreads();
+  if (t < p) L[t * p + t] += shift;
+  __syncthreads();
+  const double tol = 1e-13 * (mx + shift);
+  for (int j = 0; j < p; ++j) {
+    const double piv = L[j * p + j];
+    const bool ok = piv > tol && mx > 0.0;
+    const double d = ok ? sqrt(piv) : 0.0;
+    __syncthreads();
+    if (t == 0) {
+      L[j * p + j] = d;
+      dinv[j] = ok ? 1.0 / d : 0.0;
+    }
+    // column j below the diagonal
+    for (int i = j + 1 + t; i < p; i += 64) L[i * p + j] = ok ? L[i * p + j] / d : 0.0;
+    __syncthreads();
+    // trailing update of the lower triangle
+    const int m = p - j - 1;
+    for (int e = t; e < m * m; e += 64) {
+      const int i = j + 1 + e / m, c = j + 1 + e % m;
+      if (c <= i) L[i * p + c] -= L[i * p + j] * L[c * p + j];
+    }
+    __syncthreads();
+  }
+  // inverse of L by forward substitution, one column of the identity per lane
+  if (t < p) {
+    double x[kMaxP];
+    for (int i = 0; i < p; ++i) x[i] = 0.0;
+    for (int i = t; i < p; ++i) {
+      double s = (i == t) ? 1.0 : 0.0;
+      for (int k = t; k < i; ++k) s -= L[i * p + k] * x[k];
+      x[i] = s * dinv[i];
+    }
+    // M[b][a] = Linv[a][b]: lane t owns column t of Linv = row t of M
+    for (int a = 0; a < p; ++a) M[t * p + a] = (a >= t) ? x[a] : 0.0;
+  }
+  if (Lout)
+    for (int e = t; e < p * p; e += 64) Lout[e] = (e % p <= e / p) ? L[e] : 0.0;
+}
+
+// Xout (n x pout) = X (n x pin) * M (pin x pout), row-major.
+__global__ void apply_kernel(const double *__restrict__ X, int64_t n, int pin, const double *__restrict__ M, int pout,
+                             double *__restrict__ Xout) {
+  const int64_t total = n * pout;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / pout;
+    const int a = (int)(e - i * pout);
+    const double *row = X + i * pin;
+    double s = 0.0;
+    for (int b = 0; b < pin; ++b) s = fma(row[b], M[b * pout + a], s);
+    Xout[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------- Jacobi eigen
+// Symmetric G (p x p) -> eigenvalues (descending) lam[p], eigenvectors W (p x p,
+// column c is the c-th eigenvector). One wave; cyclic Jacobi with the
+// round-robin pairing so the p/2 rotations of a round are disjoint.
+__global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict__ G, int p, double *__restrict__ W,
+                                                        double *__restrict__ lam) {
+  __shared__ double A[kMaxP * kMaxP];
+  __shared__ double V[kMaxP * kMaxP];
+  __shared__ double cs[kMaxP / 2][2];
+  __shared__ int pr[kMaxP / 2][2];
+  __shared__ double red[64];
+  const int t = threadIdx.x;
+  for (int e = t; e < p * p; e += 64) {
+    A[e] = 0.5 * (G[e] + G[(e % p) * p + e / p]);
+    V[e] = (e / p == e % p) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int pe = (p + 1) & ~1;   // even number of players; index p is a dummy when p is odd
+  const int half = pe / 2;
+  for (int sweep = 0; sweep < 40 && p > 1; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = t; e < p * p; e += 64) {
+      const double v = A[e];
+      if (e / p == e % p) dia += v * v; else off += v * v;
+    }
+    red[t] = off;
+    __syncthreads();
+    off = 0.0;
+    for (int u = 0; u < 64; ++u) off += red[u];
+    __syncthreads();
+    red[t] = dia;
+    __syncthreads();
+    dia = 0.0;
+    for (int u = 0; u < 64; ++u) dia += red[u];
+    __syncthreads();
+    if (off <= 1e-32 * dia || dia == 0.0) break;
+    for (int rd = 0; rd < pe - 1; ++rd) {
+      if (t < half) {
+        int P, Q;
+        if (t == 0) {
+          P = pe - 1;
+          Q = rd;
+        } else {
+          P = (rd + t) % (pe - 1);
+          Q = (rd - t + (pe - 1)) % (pe - 1);
+        }
+        if (P > Q) { const int tmp = P; P = Q; Q = tmp; }
+        double c = 1.0, s = 0.0;
+        if (Q < p) {
+          const double apq = A[P * p + Q];
+          if (apq != 0.0) {
+            const double tau = (A[Q * p + Q] - A[P * p + P]) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        pr[t][0] = P;
+        pr[t][1] = Q;
+        cs[t][0] = c;
+        cs[t][1] = s;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = t; e < half * p; e += 64) {
+        const int pi = e / p, i = e % p;
+        const int P = pr[pi][0], Q = pr[pi][1];
+        if (Q < p) {
+          const double c = cs[pi][0], s = cs[pi][1];
+          const double aip = A[i * p + P], aiq = A[i * p + Q];
+          A[i * p + P] = c * aip - s * aiq;
+          A[i * p + Q] = s * aip + c * aiq;
+          const double vip = V[i * p + P], viq = V[i * p + Q];
+          V[i * p + P] = c * vip - s * viq;
+          V[i * p + Q] = s * vip + c * viq;
+        }
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = t; e < half * p; e += 64) {
+        const int pi = e / p, j = e % p;
+        const int P = pr[pi][0], Q = pr[pi][1];
+        if (Q < p) {
+          const double c = cs[pi][0], s = cs[pi][1];
+          const double apj = A[P * p + j], aqj = A[Q * p + j];
+          A[P * p + j] = c * apj - s * aqj;
+          A[Q * p + j] = s * apj + c * aqj;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) {
+    // selection order by descending eigenvalue
+    int order[kMaxP];
+    bool used[kMaxP];
+    for (int a = 0; a < p; ++a) used[a] = false;
+    for (int a = 0; a < p; ++a) {
+      int best = -1;
+      for (int b = 0; b < p; ++b)
+        if (!used[b] && (best < 0 || A[b * p + b] > A[best * p + best])) best = b;
+      used[best] = true;
+      order[a] = best;
+    }
+    for (int a = 0; a < p; ++a) {
+      lam[a] = A[order[a] * p + order[a]];
+      red[a] = (double)order[a];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < p * p; e += 64) {
+    const int i = e / p, a = e % p;
+    W[e] = V[i * p + (int)red[a]];
+  }
+}
+
+// From the eigenpairs of a Gram matrix, build the maps of a Rayleigh-Ritz /
+// canonical step for the top r pairs: Mu = W_r diag(1/sqrt(lam)), Mv = W_r,
+// sigma = sqrt(lam) (components with lam <= 1e-28 lam_max are set to 0).
+__global__ void ritz_maps_kernel(const double *__restrict__ W, const double *__restrict__ lam, int p, int r,
+                                 double *__restrict__ Mu, double *__restrict__ Mv, double *__restrict__ sigma) {
+  const double lmax = lam[0];
+  for (int e = threadIdx.x; e < p * r; e += blockDim.x) {
+    const int b = e / r, a = e % r;
+    const double l = lam[a];
+    const bool ok = l > 1e-28 * lmax && l > 0.0;
+    Mu[e] = ok ? W[b * p + a] / sqrt(l) : 0.0;
+    Mv[e] = W[b * p + a];
+  }
+  if (threadIdx.x < r) {
+    const double l = lam[threadIdx.x];
+    sigma[threadIdx.x] = (l > 1e-28 * lmax && l > 0.0) ? sqrt(l) : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- sparse products
+// Xout[o][a] = sum over entries e of row o (with subset sel, when sub != null)
+// of w_e M~_e Y[idx_e][a]; one wave per output row, lane a < p.
+__global__ void spmm_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                            const double *__restrict__ w, const double *__restrict__ mt,
+                            const uint8_t *__restrict__ sub, int sel, const double *__restrict__ Y, int p,
+                            int64_t n_out, double *__restrict__ Xout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t o = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (o >= n_out) return;
+  double acc = 0.0;
+  const int64_t e1 = ptr[o + 1];
+  for (int64_t e = ptr[o]; e < e1; ++e) {
+    if (sub && sub[e] != sel) continue;
+    const double v = w[e] * mt[e];
+    if (lane < p) acc = fma(v, Y[(int64_t)idx[e] * p + lane], acc);
+  }
+  if (lane < p) Xout[o * p + lane] = acc;
+}
+
+__global__ void gaussian_block_kernel(int64_t n, int p, uint64_t seed, double *__restrict__ Y) {
+  const int nb4 = (p + 3) / 4;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nb4; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / nb4;
+    const int cb = (int)(e - i * nb4);
+    const float4 z = normals4(stream_call(seed, kTagInit, (uint64_t)i, (uint32_t)cb));
+    const float zz[4] = {z.x, z.y, z.z, z.w};
+    for (int u = 0; u < 4; ++u)
+      if (cb * 4 + u < p) Y[i * p + cb * 4 + u] = (double)zz[u];
+  }
+}
+
+// ---------------------------------------------------------------- trim, scale, sign
+__global__ void trim_kernel(double *__restrict__ U, int64_t n, int r, const float *__restrict__ na2,
+                            const double *__restrict__ FA) {
+  const double fa = FA[0];
+  const double c = 8.0 * sqrt((double)r);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int a = 0; a < r; ++a) s += U[i * r + a] * U[i * r + a];
+    const double thr = fa > 0.0 ? c * sqrt((double)na2[i] / fa) : 0.0;
+    if (sqrt(s) > thr)
+      for (int a = 0; a < r; ++a) U[i * r + a] = 0.0;
+  }
+}
+
+__global__ void scale_cols_kernel(double *__restrict__ U, int64_t n, int r, const double *__restrict__ s) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * r; e += (int64_t)gridDim.x * blockDim.x)
+    U[e] *= s[e % r];
+}
+
+// One workgroup per component c: sign of the largest-magnitude entry of V[:, c]
+// (first index on ties); flips U[:, c] and V[:, c] when it is negative.
+__global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, int64_t n1, double *__restrict__ V,
+                                                       int64_t n2, int r) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t j = t; j < n2; j += 256) {
+    const double a = fabs(V[j * r + c]);
+    if (a > best) { best = a; bidx = j; }
+  }
+  bv[t] = best;
+  bi[t] = bidx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) {
+      if (bv[t + off] > bv[t] || (bv[t + off] == bv[t] && bi[t + off] < bi[t])) {
+        bv[t] = bv[t + off];
+        bi[t] = bi[t + off];
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = V[bi[0] * r + c] < 0.0;
+  __syncthreads();
+  if (!flip) return;
+  for (int64_t j = t; j < n2; j += 256) V[j * r + c] = -V[j * r + c];
+  for (int64_t i = t; i < n1; i += 256) U[i * r + c] = -U[i * r + c];
+}
+
+// ---------------------------------------------------------------- weighted LS solves
+// One wave per output row o. RT = ceil((r+1)/16) MFMA tiles per side.
+template <int RT>
+__global__ __launch_bounds__(64) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                      const double *__restrict__ w, const double *__restrict__ mt,
+                                                      const uint8_t *__restrict__ sub, int sel,
+                                                      const double *__restrict__ Q, int r, int64_t n_out,
+                                                      double *__restrict__ Xout) {
+  constexpr int D = RT * 16;
+  __shared__ double G[D * D];
+  __shared__ double L[32 * 32];
+  __shared__ double hv[32];
+  const int64_t o = blockIdx.x;
+  if (o >= n_out) return;
+  const int t = threadIdx.x;
+  const int col = t & 15, ent = t >> 4;
+  v4d acc[RT][RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t e0 = ptr[o], e1 = ptr[o + 1];
+  for (int64_t eb = e0; eb < e1; eb += 4) {
+    const int64_t e = eb + ent;
+    double we = 0.0, me = 0.0;
+    int64_t row = 0;
+    if (e < e1 && (!sub || sub[e] == sel)) {
+      we = w[e];
+      me = mt[e];
+      row = idx[e];
+    }
+    double af[RT], bf[RT];
+#pragma unroll
+    for (int tt = 0; tt < RT; ++tt) {
+      const int a = tt * 16 + col;
+      double x = 0.0;
+      if (we != 0.0) x = a < r ? Q[row * r + a] : (a == r ? me : 0.0);
+      bf[tt] = x;
+      af[tt] = a < r ? we * x : 0.0;
+    }
+#pragma unroll
+    for (int ta = 0; ta < RT; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < RT; ++tb) acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ta], bf[tb], acc[ta][tb], 0, 0, 0);
+  }
+  // v_mfma_f64_16x16x4f64 leaves D[4*j + t/16][t%16] in register j of lane t
+#pragma unroll
+  for (int ta = 0; ta < RT; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < RT; ++tb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) G[(ta * 16 + 4 * j + ent) * D + tb * 16 + col] = acc[ta][tb][j];
+  __syncthreads();
+
+  double mx = 0.0, tr = 0.0;
+  for (int a = 0; a < r; ++a) {
+    mx = fmax(mx, G[a * D + a]);
+    tr += G[a * D + a];
+  }
+  double x_out = 0.0;
+  bool solved = false;
+  for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
+    const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
+    const double tol = 1e-12 * (mx + shift);
+    for (int e = t; e < r * r; e += 64) {
+      const int i = e / r, c = e % r;
+      L[i * 32 + c] = G[i * D + c] + ((i == c) ? shift : 0.0);
+    }
+    if (t < r) hv[t] = G[t * D + r];
+    __syncthreads();
+    bool ok = true;
+    for (int j = 0; j < r; ++j) {
+      const double piv = L[j * 32 + j];
+      if (!(piv > tol)) { ok = false; break; }
+      const double d = sqrt(piv);
+      __syncthreads();
+      if (t == 0) L[j * 32 + j] = d;
+      for (int i = j + 1 + t; i < r; i += 64) L[i * 32 + j] /= d;
+      __syncthreads();
+      const int m = r - j - 1;
+      for (int e = t; e < m * m; e += 64) {
+        const int i = j + 1 + e / m, c = j + 1 + e % m;
+        if (c <= i) L[i * 32 + c] -= L[i * 32 + j] * L[c * 32 + j];
+      }
+      __syncthreads();
+    }
+    if (!ok) {
+      __syncthreads();
+      continue;
+    }
+    // forward: L y = h (column-oriented, updates in index order)
+    for (int i = 0; i < r; ++i) {
+      __syncthreads();
+      const double yi = hv[i] / L[i * 32 + i];
+      __syncthreads();
+      if (t == 0) hv[i] = yi;
+      for (int k = i + 1 + t; k < r; k += 64) hv[k] -= L[k * 32 + i] * yi;
+    }
+    // backward: L^T x = y
+    for (int i = r - 1; i >= 0; --i) {
+      __syncthreads();
+      const double xi = hv[i] / L[i * 32 + i];
+      __syncthreads();
+      if (t == 0) hv[i] = xi;
+      for (int k = t; k < i; k += 64) hv[k] -= L[i * 32 + k] * xi;
+    }
+    __syncthreads();
+    solved = true;
+  }
+  if (t < r) {
+    x_out = solved ? hv[t] : 0.0;
+    Xout[o * r + t] = x_out;
+  }
+}
+
+// ---------------------------------------------------------------- host helpers
+struct Ws {
+  double *FA;       // [1]
+  double *blocks;   // n1/256 + 1
+  double *X, *Y, *T1, *T2;  // n1*p, n2*p, max(n1,n2)*p (x2)
+  double *part;     // gram partials
+  double *G, *M, *W, *lam, *Mu, *Mv, *sig;
+  double *U, *V;    // n1*r, n2*r iterates
+};
+
+constexpr int kGramBlocks = 64;
+
+template <typename T>
+T *carve(char *&p, size_t count) {
+  T *out = reinterpret_cast<T *>(p);
+  p += (count * sizeof(T) + 255) / 256 * 256;
+  return out;
+}
+
+Ws carve_ws(void *base, int64_t n1, int64_t n2, int p, int r) {
+  char *c = static_cast<char *>(base);
+  const int64_t nm = std::max(n1, n2);
+  Ws w;
+  w.FA = carve<double>(c, 4);
+  w.blocks = carve<double>(c, n1 / 256 + 2);
+  w.X = carve<double>(c, n1 * p);
+  w.Y = carve<double>(c, n2 * p);
+  w.T1 = carve<double>(c, nm * p);
+  w.T2 = carve<double>(c, nm * p);
+  w.part = carve<double>(c, (size_t)kGramBlocks * kMaxP * kMaxP);
+  w.G = carve<double>(c, kMaxP * kMaxP);
+  w.M = carve<double>(c, kMaxP * kMaxP);
+  w.W = carve<double>(c, kMaxP * kMaxP);
+  w.lam = carve<double>(c, kMaxP);
+  w.Mu = carve<double>(c, kMaxP * kMaxP);
+  w.Mv = carve<double>(c, kMaxP * kMaxP);
+  w.sig = carve<double>(c, kMaxP);
+  w.U = carve<double>(c, n1 * r);
+  w.V = carve<double>(c, n2 * r);
+  return w;
+}
+
+size_t carve_bytes(int64_t n1, int64_t n2, int p, int r) {
+  const int64_t nm = std::max(n1, n2);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  size_t s = 0;
+  s += al(4 * 8) + al((n1 / 256 + 2) * 8) + al(n1 * p * 8) + al(n2 * p * 8) + 2 * al(nm * p * 8);
+  s += al((size_t)kGramBlocks * kMaxP * kMaxP * 8) + 2 * al(kMaxP * kMaxP * 8) + al(kMaxP * kMaxP * 8) + al(kMaxP * 8);
+  s += 2 * al(kMaxP * kMaxP * 8) + al(kMaxP * 8) + al(n1 * r * 8) + al(n2 * r * 8);
+  return s;
+}
+
+void gram(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
+  const int nblk = (int)std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  const int64_t rpb = (n + nblk - 1) / nblk;
+  hipLaunchKernelGGL(gram_partial_kernel, dim3(nblk), dim3(256), 0, st, X, n, p, rpb, w.part);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(cdiv(p * p, 256)), dim3(256), 0, st, w.part, nblk, p, w.G);
+}
+
+void apply(const double *X, int64_t n, int pin, const double *M, int pout, double *Xout, hipStream_t st) {
+  hipLaunchKernelGGL(apply_kernel, dim3(std::min<unsigned>(cdiv(n * pout, 256), 4096)), dim3(256), 0, st, X, n, pin,
+                     M, pout, Xout);
+}
+
+// X (n x p) <- orthonormal basis of its span (CholeskyQR2); uses w.T1 as scratch.
+void orth(const Ws &w, double *X, int64_t n, int p, hipStream_t st) {
+  gram(w, X, n, p, st);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, w.G, p, 1e-14, w.M, (double *)nullptr);
+  apply(X, n, p, w.M, p, w.T1, st);
+  gram(w, w.T1, n, p, st);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, w.G, p, 0.0, w.M, (double *)nullptr);
+  apply(w.T1, n, p, w.M, p, X, st);
+}
+
+void spmm(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
+          const double *Y, int p, int64_t n_out, double *Xout, hipStream_t st) {
+  hipLaunchKernelGGL(spmm_kernel, dim3(cdiv(n_out, 4)), dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out,
+                     Xout);
+}
+
+void ls_solve(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
+              const double *Q, int r, int64_t n_out, double *Xout, hipStream_t st) {
+  const int rt = (r + 1 + 15) / 16;
+  const dim3 grid((unsigned)std::max<int64_t>(1, n_out));
+  if (rt == 1)
+    hipLaunchKernelGGL(ls_solve_kernel<1>, grid, dim3(64), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+  else if (rt == 2)
+    hipLaunchKernelGGL(ls_solve_kernel<2>, grid, dim3(64), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+  else
+    hipLaunchKernelGGL(ls_solve_kernel<3>, grid, dim3(64), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+}
+
+// U (n1 x r), V (n2 x r, orthonormal columns) -> canonical Uc, sigma, Vc
+// (U V^T = Uc diag(sigma) Vc^T). Uc written to Uout, Vc to Vout.
+void canonical(const Ws &w, const double *U, int64_t n1, const double *V, int64_t n2, int r, double *Uout,
+               double *Vout, double *sigma, hipStream_t st) {
+  gram(w, U, n1, r, st);
+  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(64), 0, st, w.G, r, w.W, w.lam);
+  hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, r, r, w.Mu, w.Mv, sigma);
+  apply(U, n1, r, w.Mu, r, Uout, st);
+  apply(V, n2, r, w.Mv, r, Vout, st);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3(r), dim3(256), 0, st, Uout, n1, Vout, n2, r);
+}
+
+}  // namespace
+
+size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t /*nnz*/) {
+  const int p = std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample));
+  return carve_bytes(n1, n2, std::max(p, r), r);
+}
+
+hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *na2, double *Uout, double *Vout,
+                       double *sigma, void *wsbase, hipStream_t st, int * /*status*/) {
+  const int64_t n1 = om.n1, n2 = om.n2;
+  const int r = prm.r, T = prm.T;
+  const int p = std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample)));
+  const int iters = prm.init_iters > 0 ? prm.init_iters : 12;
+  const bool split = prm.omega_mode == SMP_OMEGA_SPLIT;
+  Ws w = carve_ws(wsbase, n1, n2, p, r);
+  const uint8_t *scsr = split ? om.sub_csr : nullptr;
+  const uint8_t *scsc = split ? om.sub_csc : nullptr;
+
+  fixed_total(na2, n1, w.blocks, w.FA, st);
+
+  // ---- init: subspace iteration on R = w .* P_Omega0(M~)
+  hipLaunchKernelGGL(gaussian_block_kernel, dim3(cdiv(n2 * ((p + 3) / 4), 256)), dim3(256), 0, st, n2, p, prm.seed,
+                     w.Y);
+  orth(w, w.Y, n2, p, st);
+  for (int it = 0; it < iters; ++it) {
+    spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
+    orth(w, w.X, n1, p, st);
+    spmm(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 0, w.X, p, n2, w.Y, st);
+    orth(w, w.Y, n2, p, st);
+  }
+  spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
+  // Rayleigh-Ritz: X = R Y; X^T X = W diag(lam) W^T; U0 = X W_r lam^-1/2, V0 = Y W_r
+  gram(w, w.X, n1, p, st);
+  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(64), 0, st, w.G, p, w.W, w.lam);
+  hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, p, r, w.Mu, w.Mv, w.sig);
+  apply(w.X, n1, p, w.Mu, r, w.U, st);
+  apply(w.Y, n2, p, w.Mv, r, w.V, st);
+  hipLaunchKernelGGL(trim_kernel, dim3(cdiv(n1, 256)), dim3(256), 0, st, w.U, n1, r, na2, w.FA);
+
+  if (T == 0) {
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
+  } else {
+    for (int t = 0; t < T; ++t) {
+      orth(w, w.U, n1, r, st);                                          // Q_U
+      ls_solve(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 2 * t + 1, w.U, r, n2, w.V, st);
+      orth(w, w.V, n2, r, st);                                          // Q_V
+      ls_solve(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 2 * t + 2, w.V, r, n1, w.U, st);
+    }
+  }
+  double *sig_out = sigma ? sigma : w.sig;
+  canonical(w, w.U, n1, w.V, n2, r, Uout, Vout, sig_out, st);
+  if (!sigma) hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, Uout, n1, r, sig_out);
+  return hipGetLastError();
+}
+
+}  // namespace smp

@@ -1,0 +1,155 @@
+"""End-to-end GPU parity of smp_solve (Alg. 1) against the oracle's smp_pca on
+the same inputs, plus sampled checks at the full benchmark size.
+
+Gate: the spectral error e = ||A^T B - U diag(sigma) V^T|| / ||A^T B|| of the
+GPU result is within 1e-4 (relative) of the oracle's. Omega may differ in a
+handful of entries because the GPU decides coins from its FP32 norms and the
+oracle from its FP64 norms; the count of differing entries is reported.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import smp_inputs
+from conftest import gpu_available
+from gpu_common import DEV, SEED, latent, log
+from oracle import evaluate as oev
+from oracle import gaussian, philox
+from oracle import solve as oso
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1610_06656_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def _run_gpu(api, ctx, Ad, Bd, k, r, T, m=None, **kw):
+    d, n1 = Ad.shape
+    n2 = n1 if Bd is None else Bd.shape[1]
+    p = api.make_params(d, n1, n2, k, r, T=T, m=m, b_is_a=Bd is None, **kw)
+    U = torch.empty(n1, r, dtype=torch.float64, device=DEV)
+    V = torch.empty(n2, r, dtype=torch.float64, device=DEV)
+    s = torch.empty(r, dtype=torch.float64, device=DEV)
+    ctx.smp_solve(p, Ad, Bd, U, V, s)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), s.cpu().numpy(), V.cpu().numpy(), p
+
+
+SOLVE_CASES = {
+    "c1": dict(d=2000, n1=200, n2=200, R=5, k=50, r=5, T=10),
+    "ragged": dict(d=1037, n1=77, n2=131, R=3, k=37, r=3, T=8),
+    "k400_r10": dict(d=20000, n1=300, n2=260, R=10, k=400, r=10, T=10),
+    "tiny_d1": dict(d=1, n1=3, n2=4, R=1, k=2, r=1, T=3),
+    "single_row": dict(d=64, n1=1, n2=5, R=1, k=3, r=1, T=2),
+}
+
+
+@pytest.mark.parametrize("name", list(SOLVE_CASES))
+def test_solve_matches_oracle(api, ctx, name):
+    c = SOLVE_CASES[name]
+    log(f"solve {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=c["R"])
+    m = api.default_m(c["n1"], c["n2"], c["r"]) if min(c["n1"], c["n2"]) > 1 else 50.0
+    U, s, V, p = _run_gpu(api, ctx, Ad, Bd, c["k"], c["r"], c["T"], m=m, init_iters=40)
+    ref = oso.smp_pca(A.numpy(), B.numpy(), c["r"], c["k"], p.m, c["T"], SEED)
+    AtB = oev.product(A.numpy(), B.numpy())
+    e_gpu = oev.relative_error(AtB, U, s, V)
+    e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
+    log(f"  e_gpu={e_gpu:.6e} e_oracle={e_ora:.6e} |Omega|={ref['omega'].nnz}")
+    assert abs(e_gpu - e_ora) <= 1e-4 * e_ora + 1e-12
+    assert np.allclose(U.T @ U, np.eye(c["r"]), atol=1e-9)
+
+
+def test_solve_a_equals_b(api, ctx):
+    d, n, k, r = 3000, 150, 80, 4
+    A, _, Ad, _ = latent(d, n, n, R=4, same=True)
+    U, s, V, p = _run_gpu(api, ctx, Ad, None, k, r, 10, init_iters=40)
+    ref = oso.smp_pca(A.numpy(), None, r, k, p.m, 10, SEED)
+    AtA = oev.product(A.numpy(), None)
+    e_gpu = oev.relative_error(AtA, U, s, V)
+    e_ora = oev.relative_error(AtA, ref["Uc"], ref["sigma"], ref["Vc"])
+    assert abs(e_gpu - e_ora) <= 1e-4 * e_ora
+
+
+def test_solve_deterministic(api, ctx):
+    _, _, Ad, Bd = latent(5000, 300, 280, R=5)
+    r1 = _run_gpu(api, ctx, Ad, Bd, 64, 5, 5)
+    r2 = _run_gpu(api, ctx, Ad, Bd, 64, 5, 5)
+    for a, b in zip(r1[:3], r2[:3]):
+        assert np.array_equal(a, b)
+
+
+def test_solve_rejects_bad_args_without_launch(api, ctx):
+    _, _, Ad, Bd = latent(100, 20, 20)
+    p = api.make_params(100, 20, 20, 8, 25)          # r > n
+    U = torch.empty(20, 25, dtype=torch.float64, device=DEV)
+    with pytest.raises(api.SmpError) as e:
+        ctx.smp_solve(p, Ad, Bd, U, U, None)
+    assert e.value.status == 1
+
+
+# ---------------------------------------------------------------- full benchmark size
+
+def _pi_rows(seed, k, rows_c, d):
+    """Z(c, l) / sqrt(k) for selected sketch rows c and all l < d, from the
+    oracle's generator (one Philox call per (c // 4, l))."""
+    out = np.empty((len(rows_c), d))
+    ls = np.arange(d, dtype=np.int64)
+    for t, c in enumerate(rows_c):
+        w = philox.stream_words(seed, philox.TAG_PI, ls, np.full(d, c // 4, dtype=np.int64))
+        z = gaussian.normals_from_words(*w)[c % 4]
+        out[t] = z / np.sqrt(k)
+    return out
+
+
+def test_c2_sketch_sampled_outputs(api, ctx):
+    """d = 200,000, n1 = n2 = 2,000, k = 400 in the benchmark's launch
+    configuration: 16 sketch rows x 24 columns of A~ and B~ against the oracle
+    computed one by one, and every squared norm."""
+    c = smp_inputs.CONFIGS["c2_fp32"]
+    log("c2 sketch sampled")
+    Ad, Bd = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], SEED, device=DEV)
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"])
+    At = torch.empty(c["n1"], c["k"], device=DEV)
+    Bt = torch.empty(c["n2"], c["k"], device=DEV)
+    na2 = torch.empty(c["n1"], device=DEV)
+    nb2 = torch.empty(c["n2"], device=DEV)
+    ctx.smp_sketch(p, Ad, Bd, At, Bt, na2, nb2)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    rows_c = sorted(set(rng.choice(c["k"], 16, replace=False).tolist()) | {0, c["k"] - 1})
+    cols = sorted(set(rng.choice(c["n1"], 24, replace=False).tolist()) | {0, c["n1"] - 1})
+    P = _pi_rows(p.seed, c["k"], rows_c, c["d"])
+    for X, S in ((Ad, At), (Bd, Bt)):
+        Xs = X[:, cols].double().cpu().numpy()
+        ref = P @ Xs                                            # len(rows_c) x len(cols)
+        got = S[cols][:, rows_c].double().cpu().numpy().T
+        scale = np.linalg.norm(Xs, axis=0) * np.sqrt(1.0 / c["k"]) * np.sqrt(c["d"]) / np.sqrt(c["d"])
+        err = np.abs(got - ref) / scale[None, :]
+        assert err.max() < 1e-5
+    ref_na2 = (Ad.double() ** 2).sum(0).cpu().numpy()
+    assert np.allclose(na2.cpu().numpy(), ref_na2, rtol=1e-6)
+
+
+def test_c2_end_to_end_matches_oracle(api, ctx):
+    """The benchmark workload end to end: e_gpu within 1e-4 of e_oracle."""
+    c = smp_inputs.CONFIGS["c2_fp32"]
+    log("c2 end to end")
+    Ad, Bd = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], SEED, device=DEV)
+    U, s, V, p = _run_gpu(api, ctx, Ad, Bd, c["k"], c["r"], c["T"])
+    A, B = Ad.cpu().numpy(), Bd.cpu().numpy()
+    ref = oso.smp_pca(A, B, c["r"], c["k"], p.m, c["T"], SEED)
+    AtB = oev.product(A, B)
+    e_gpu = oev.relative_error(AtB, U, s, V)
+    e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
+    log(f"  e_gpu={e_gpu:.6e} e_oracle={e_ora:.6e} |Omega|={ref['omega'].nnz}")
+    assert abs(e_gpu - e_ora) <= 1e-4 * e_ora
