@@ -8,11 +8,17 @@
 // product is exact in FP64), the cosine is clamped to [-1, 1], and
 // M~ = s_i s_j cos. A column with a zero norm (data or sketch) gives M~ = 0.
 //
-// The estimate is a gather-dot over the sampled entries: one wave per row of
-// the CSR listing (resp. column of the CSC listing), a quarter-wave of 16
-// lanes per entry, lane u of the quarter summing components u, u+16, ... The
-// CSR and CSC kernels use the same lane split and reduction tree, so the two
-// listings carry bit-identical M~ values.
+// Two ways to evaluate the sampled dot products, both writing bit-identical
+// values into the CSR and CSC listings:
+//  * dense tiles (Omega covers at least 1/32 of the grid): a workgroup
+//    computes a 64 x 64 block of A~^T B~ on the FP64 matrix cores
+//    (v_mfma_f64_16x16x4f64, FP32 sketch entries widened exactly) and writes
+//    the estimates of the sampled entries of that block, found by binary
+//    search in each row's (column's) sorted listing;
+//  * gather (sparse grids): one wave per row of the CSR listing (resp. column
+//    of the CSC listing), a quarter-wave of 16 lanes per entry, lane u of the
+//    quarter summing components u, u+16, ...; the CSR and CSC kernels share
+//    the lane split and reduction tree.
 #include <algorithm>
 
 #include "smp_device.hpp"
@@ -95,6 +101,85 @@ __global__ void estimate_cols_kernel(const int64_t *__restrict__ ptr, const int3
   }
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kTS = 64, kKCH = 32;
+
+__device__ __forceinline__ int64_t lower_bound_idx(const int32_t *__restrict__ a, int64_t lo, int64_t hi, int64_t key) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void estimate_tiles_kernel(
+    const float *__restrict__ At, const float *__restrict__ Bt, int64_t n1, int64_t n2, int k,
+    const double *__restrict__ na, const double *__restrict__ nb, const double *__restrict__ sa,
+    const double *__restrict__ sb, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const int64_t *__restrict__ cp, const int32_t *__restrict__ ri, double *__restrict__ mt_csr,
+    double *__restrict__ mt_csc) {
+  __shared__ float sA[kTS][kKCH + 1];
+  __shared__ float sB[kTS][kKCH + 1];
+  __shared__ double dot[kTS][kTS + 1];
+  const int64_t i0 = (int64_t)blockIdx.y * kTS, j0 = (int64_t)blockIdx.x * kTS;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wm = wave >> 1, wn = wave & 1;   // 32 x 32 quadrant of the block
+  const int m = lane & 15, kk = lane >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < k; c0 += kKCH) {
+    for (int e = t; e < kTS * kKCH; e += 256) {
+      const int rr = e / kKCH, cc = e % kKCH;
+      const int c = c0 + cc;
+      const int64_t i = i0 + rr, j = j0 + rr;
+      sA[rr][cc] = (i < n1 && c < k) ? At[i * k + c] : 0.0f;
+      sB[rr][cc] = (j < n2 && c < k) ? Bt[j * k + c] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKCH; ks += 4) {
+      const double a0 = sA[wm * 32 + m][ks + kk], a1 = sA[wm * 32 + 16 + m][ks + kk];
+      const double b0 = sB[wn * 32 + m][ks + kk], b1 = sB[wn * 32 + 16 + m][ks + kk];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // v_mfma_f64_16x16x4f64 leaves D[4*j + t/16][t%16] in register j of lane t
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) dot[wm * 32 + 16 * a + 4 * jj + kk][wn * 32 + 16 * b + m] = acc[a][b][jj];
+  __syncthreads();
+  if (t < kTS) {
+    const int64_t i = i0 + t;
+    if (i < n1) {
+      const int64_t end = rp[i + 1];
+      for (int64_t e = lower_bound_idx(ci, rp[i], end, j0); e < end && ci[e] < j0 + kTS; ++e) {
+        const int64_t j = ci[e];
+        mt_csr[e] = rescaled(sa[i], sb[j], na[i], nb[j], dot[t][j - j0]);
+      }
+    }
+  } else if (t < 2 * kTS) {
+    const int64_t j = j0 + (t - kTS);
+    if (j < n2) {
+      const int64_t end = cp[j + 1];
+      for (int64_t e = lower_bound_idx(ri, cp[j], end, i0); e < end && ri[e] < i0 + kTS; ++e) {
+        const int64_t i = ri[e];
+        mt_csc[e] = rescaled(sa[i], sb[j], na[i], nb[j], dot[i - i0][t - kTS]);
+      }
+    }
+  }
+}
+
 inline unsigned waves_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 3) / 4); }
 
 }  // namespace
@@ -105,7 +190,12 @@ hipError_t estimate_run(const float *At, const float *Bt, const float *na2, cons
   hipLaunchKernelGGL(column_scale_kernel, dim3(waves_grid(n1)), dim3(256), 0, st, At, na2, n1, k, na, sa);
   if (nb != na)
     hipLaunchKernelGGL(column_scale_kernel, dim3(waves_grid(n2)), dim3(256), 0, st, Bt, nb2, n2, k, nb, sb);
-  if (om.nnz > 0) {
+  const bool dense = (double)om.nnz * 32.0 >= (double)n1 * (double)n2;
+  if (om.nnz > 0 && dense) {
+    const dim3 grid((unsigned)((n2 + kTS - 1) / kTS), (unsigned)((n1 + kTS - 1) / kTS));
+    hipLaunchKernelGGL(estimate_tiles_kernel, grid, dim3(256), 0, st, At, Bt, n1, n2, k, na, nb, sa, sb, om.row_ptr,
+                       om.col_idx, om.col_ptr, om.row_idx, om.mt_csr, om.mt_csc);
+  } else if (om.nnz > 0) {
     hipLaunchKernelGGL(estimate_rows_kernel, dim3(waves_grid(n1)), dim3(256), 0, st, om.row_ptr, om.col_idx, At, Bt,
                        na, nb, sa, sb, n1, k, om.mt_csr);
     hipLaunchKernelGGL(estimate_cols_kernel, dim3(waves_grid(n2)), dim3(256), 0, st, om.col_ptr, om.row_idx, At, Bt,

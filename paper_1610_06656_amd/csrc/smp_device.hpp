@@ -45,14 +45,15 @@ __device__ __forceinline__ u32x4 stream_call(uint64_t seed, uint32_t tag, uint64
 
 // Box-Muller pair: u = ((a>>8)+1) 2^-24 in (0,1], phi = (b>>8) 2^-24 in [0,1),
 // rad = sqrt(-2 ln u); returns rad*cos(2 pi phi), rad*sin(2 pi phi).
+// Uses the hardware transcendentals: v_log_f32 (log2), v_sqrt_f32, and
+// v_sin_f32 / v_cos_f32, whose argument is in revolutions, so phi is passed
+// as is.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& zc, float& zs) {
   const float u = (float)((a >> 8) + 1u) * 0x1p-24f;
-  const float twophi = (float)(b >> 8) * 0x1p-23f;  // 2*phi, exact
-  const float rad = sqrtf(-2.0f * logf(u));
-  float s, c;
-  sincospif(twophi, &s, &c);
-  zc = rad * c;
-  zs = rad * s;
+  const float phi = (float)(b >> 8) * 0x1p-24f;
+  const float rad = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u));  // -2 ln 2 log2 u
+  zc = rad * __builtin_amdgcn_cosf(phi);
+  zs = rad * __builtin_amdgcn_sinf(phi);
 }
 
 // The four N(0,1) variates of one Philox call, in lane order 0..3.

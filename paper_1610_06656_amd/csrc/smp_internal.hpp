@@ -30,8 +30,10 @@ struct SketchPlan {
   int mt_total;   // ceil(k/16) m-tiles of 16 sketch rows
   int kt;         // WG chunks along k
   int mt;         // m-tiles per chunk
-  int nv;         // columns per lane (2 or 4): a wave covers 16*nv columns
-  int ncol_tile;  // columns per WG = 4 waves * 16 * nv
+  int nv;         // adjacent columns per lane: a wave covers 16*nv columns
+  int waves;      // waves per workgroup (4 or 8), sharing one Pi block
+  int kc;         // data rows per streaming chunk (16 or 32)
+  int ncol_tile;  // columns per WG = waves * 16 * nv
   int kpad;       // mt_total * 16
 };
 

@@ -17,9 +17,12 @@
 // fails, the factorisation is retried once on G + 1e-9 trace(G)/r I, and a row
 // that still fails or has no samples gets 0. One wave owns one row.
 //
-// Orthonormalisation is CholeskyQR2 (Fukaya et al. 2014): Gram X^T X (fixed
-// reduction order), LDS Cholesky, X <- X L^-T, twice. A pivot below 1e-13 of
-// the largest diagonal entry drops that direction (its column becomes 0).
+// Orthonormalisation is CholeskyQR (Fukaya et al. 2014): Gram X^T X (fixed
+// reduction order), LDS Cholesky, X <- X L^-T. A pivot below 1e-13 of the
+// largest diagonal entry drops that direction (its column becomes 0). The
+// fixed factor of a half-step and the inner subspace iterations take one pass
+// (only the span matters there); factors that must be orthonormal (the final
+// V, the last block of the init) take two (CholeskyQR2).
 // Small symmetric eigenproblems use a parallel cyclic Jacobi method
 // (round-robin ordering, one wave).
 //
@@ -47,15 +50,22 @@ constexpr int kInitOversample = 10;
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)std::max<int64_t>(1, (a + b - 1) / b); }
 
 // ---------------------------------------------------------------- Gram
-// part[b][a*p + c] = sum over rows of block b of X[i][a] X[i][c]
+// part[b][a*p + c] = sum over the rows of block b of X[i][a] X[i][c]. Thread t
+// owns the entries t, t+256, ... of the p x p result; rows are staged in LDS.
 __global__ __launch_bounds__(256) void gram_partial_kernel(const double *__restrict__ X, int64_t n, int p,
                                                            int64_t rows_per_block, double *__restrict__ part) {
   __shared__ double rows[32 * kMaxP];
   const int t = threadIdx.x;
   const int pp = p * p;
+  int ia[16], ib[16];
   double acc[16];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  for (int u = 0; u < 16; ++u) {
+    const int idx = t + 256 * u;
+    ia[u] = idx < pp ? idx / p : 0;
+    ib[u] = idx < pp ? idx % p : 0;
+    acc[u] = 0.0;
+  }
   const int64_t r0 = blockIdx.x * rows_per_block;
   const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_block);
   for (int64_t base = r0; base < r1; base += 32) {
@@ -65,10 +75,8 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const double *__restr
     for (int rr = 0; rr < nr; ++rr) {
       const double *row = rows + rr * p;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int idx = t + 256 * u;
-        if (idx < pp) acc[u] = fma(row[idx / p], row[idx % p], acc[u]);
-      }
+      for (int u = 0; u < 16; ++u)
+        if (t + 256 * u < pp) acc[u] = fma(row[ia[u]], row[ib[u]], acc[u]);
     }
     __syncthreads();
   }
@@ -89,14 +97,28 @@ __global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, in
 }
 
 // ---------------------------------------------------------------- Cholesky -> L^-T
-// One wave. G (p x p) -> M = L^-T (upper triangular), X M has orthonormal
-// columns when X^T X = G. shift_rel > 0 adds shift_rel * trace/p to the diagonal.
-__global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__ G, int p, double shift_rel,
-                                                      double *__restrict__ M, double *__restrict__ Lout) {
+// One workgroup: sums the nblk Gram partials (fixed order) into G, adds
+// shift_rel * trace/p to the diagonal when shift_rel > 0, factors G = L L^T
+// (right-looking; a pivot <= 1e-13 of the largest diagonal entry drops that
+// direction), inverts L by forward substitution (one column per thread) and
+// writes M = L^-T, so that X M has orthonormal columns when X^T X = G.
+__global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict__ part, int nblk, int p,
+                                                       double shift_rel, double *__restrict__ M) {
   __shared__ double L[kMaxP * kMaxP];
+  __shared__ double Y[kMaxP * kMaxP];
   __shared__ double dinv[kMaxP];
   const int t = threadIdx.x;
-  for (int e = t; e < p * p; e += 64) L[e] = G[e];
+  const int pp = p * p;
+  for (int idx = t; idx < pp; idx += 256) {
+    // four independent partial sums keep several loads in flight
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 4 <= nblk; b += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += part[(int64_t)(b + u) * pp + idx];
+    for (; b < nblk; ++b) s4[0] += part[(int64_t)b * pp + idx];
+    L[idx] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  }
   __syncthreads();
   double tr = 0.0, mx = 0.0;
   for (int a = 0; a < p; ++a) {
@@ -117,45 +139,46 @@ __global__ __launch_bounds__(64) void chol_inv_kernel(const double *__restrict__
       L[j * p + j] = d;
       dinv[j] = ok ? 1.0 / d : 0.0;
     }
-    // column j below the diagonal
-    for (int i = j + 1 + t; i < p; i += 64) L[i * p + j] = ok ? L[i * p + j] / d : 0.0;
+    for (int i = j + 1 + t; i < p; i += 256) L[i * p + j] = ok ? L[i * p + j] / d : 0.0;
     __syncthreads();
-    // trailing update of the lower triangle
     const int m = p - j - 1;
-    for (int e = t; e < m * m; e += 64) {
+    for (int e = t; e < m * m; e += 256) {
       const int i = j + 1 + e / m, c = j + 1 + e % m;
       if (c <= i) L[i * p + c] -= L[i * p + j] * L[c * p + j];
     }
     __syncthreads();
   }
-  // inverse of L by forward substitution, one column of the identity per lane
+  // Y = L^-1, column t by thread t: Y[i][t] = (delta_it - sum_{t<=k<i} L[i][k] Y[k][t]) / L[i][i]
   if (t < p) {
-    double x[kMaxP];
-    for (int i = 0; i < p; ++i) x[i] = 0.0;
+    for (int i = 0; i < t; ++i) Y[i * p + t] = 0.0;
     for (int i = t; i < p; ++i) {
       double s = (i == t) ? 1.0 : 0.0;
-      for (int k = t; k < i; ++k) s -= L[i * p + k] * x[k];
-      x[i] = s * dinv[i];
+      for (int k = t; k < i; ++k) s -= L[i * p + k] * Y[k * p + t];
+      Y[i * p + t] = s * dinv[i];
     }
-    // M[b][a] = Linv[a][b]: lane t owns column t of Linv = row t of M
-    for (int a = 0; a < p; ++a) M[t * p + a] = (a >= t) ? x[a] : 0.0;
   }
-  if (Lout)
-    for (int e = t; e < p * p; e += 64) Lout[e] = (e % p <= e / p) ? L[e] : 0.0;
+  __syncthreads();
+  // M[b][a] = Y[a][b]
+  for (int idx = t; idx < pp; idx += 256) {
+    const int b = idx / p, a = idx % p;
+    M[idx] = Y[a * p + b];
+  }
 }
 
-// Xout (n x pout) = X (n x pin) * M (pin x pout), row-major.
-__global__ void apply_kernel(const double *__restrict__ X, int64_t n, int pin, const double *__restrict__ M, int pout,
-                             double *__restrict__ Xout) {
-  const int64_t total = n * pout;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / pout;
-    const int a = (int)(e - i * pout);
-    const double *row = X + i * pin;
-    double s = 0.0;
-    for (int b = 0; b < pin; ++b) s = fma(row[b], M[b * pout + a], s);
-    Xout[e] = s;
-  }
+// Xout (n x pout) = X (n x pin) * M (pin x pout), row-major. One wave per row,
+// lane a computes output column a; every lane reads the whole input row before
+// any lane writes, so Xout may alias X when pin == pout.
+__global__ void apply_kernel(const double *X, int64_t n, int pin, const double *__restrict__ M, int pout,
+                             double *Xout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double *row = X + i * pin;
+  double s = 0.0;
+  if (lane < pout)
+    for (int b = 0; b < pin; ++b) s = fma(row[b], M[b * pout + lane], s);
+  __builtin_amdgcn_wave_barrier();
+  if (lane < pout) Xout[i * pout + lane] = s;
 }
 
 // ---------------------------------------------------------------- Jacobi eigen
@@ -183,16 +206,8 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
       const double v = A[e];
       if (e / p == e % p) dia += v * v; else off += v * v;
     }
-    red[t] = off;
-    __syncthreads();
-    off = 0.0;
-    for (int u = 0; u < 64; ++u) off += red[u];
-    __syncthreads();
-    red[t] = dia;
-    __syncthreads();
-    dia = 0.0;
-    for (int u = 0; u < 64; ++u) dia += red[u];
-    __syncthreads();
+    off = wave_sum(off);
+    dia = wave_sum(dia);
     if (off <= 1e-32 * dia || dia == 0.0) break;
     for (int rd = 0; rd < pe - 1; ++rd) {
       if (t < half) {
@@ -250,22 +265,16 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
       __syncthreads();
     }
   }
-  if (t == 0) {
-    // selection order by descending eigenvalue
-    int order[kMaxP];
-    bool used[kMaxP];
-    for (int a = 0; a < p; ++a) used[a] = false;
-    for (int a = 0; a < p; ++a) {
-      int best = -1;
-      for (int b = 0; b < p; ++b)
-        if (!used[b] && (best < 0 || A[b * p + b] > A[best * p + best])) best = b;
-      used[best] = true;
-      order[a] = best;
+  // descending order: eigenvalue a goes to position rank(a) (ties by index)
+  if (t < p) {
+    const double la = A[t * p + t];
+    int rank = 0;
+    for (int b = 0; b < p; ++b) {
+      const double lb = A[b * p + b];
+      rank += (lb > la || (lb == la && b < t)) ? 1 : 0;
     }
-    for (int a = 0; a < p; ++a) {
-      lam[a] = A[order[a] * p + order[a]];
-      red[a] = (double)order[a];
-    }
+    lam[rank] = la;
+    red[rank] = (double)t;
   }
   __syncthreads();
   for (int e = t; e < p * p; e += 64) {
@@ -294,23 +303,52 @@ __global__ void ritz_maps_kernel(const double *__restrict__ W, const double *__r
 }
 
 // ---------------------------------------------------------------- sparse products
-// Xout[o][a] = sum over entries e of row o (with subset sel, when sub != null)
-// of w_e M~_e Y[idx_e][a]; one wave per output row, lane a < p.
-__global__ void spmm_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                            const double *__restrict__ w, const double *__restrict__ mt,
-                            const uint8_t *__restrict__ sub, int sel, const double *__restrict__ Y, int p,
-                            int64_t n_out, double *__restrict__ Xout) {
-  const int lane = threadIdx.x & 63;
-  const int64_t o = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+// Xout[o][a] = sum over the entries e of row o (those of subset sel when sub
+// is given) of w_e M~_e Y[idx_e][a]. One workgroup (4 waves) per output row;
+// each wave takes every fourth chunk of 64 entries, loads the chunk's metadata
+// one entry per lane, and lets groups of G lanes (G >= p) take one entry each
+// and load its row of Y, 8 entries in flight per group. Partial sums are
+// combined with shuffles within a wave and through LDS across waves.
+template <int G>
+__global__ __launch_bounds__(256) void spmm_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                   const double *__restrict__ w, const double *__restrict__ mt,
+                                                   const uint8_t *__restrict__ sub, int sel,
+                                                   const double *__restrict__ Y, int p, int64_t n_out,
+                                                   double *__restrict__ Xout) {
+  constexpr int NG = 64 / G;
+  __shared__ double red[4 * 64];
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int g = lane / G, a = lane % G;
+  const int64_t o = blockIdx.x;
   if (o >= n_out) return;
+  const int64_t e0 = ptr[o], e1 = ptr[o + 1];
   double acc = 0.0;
-  const int64_t e1 = ptr[o + 1];
-  for (int64_t e = ptr[o]; e < e1; ++e) {
-    if (sub && sub[e] != sel) continue;
-    const double v = w[e] * mt[e];
-    if (lane < p) acc = fma(v, Y[(int64_t)idx[e] * p + lane], acc);
+  for (int64_t eb = e0 + 64 * wave; eb < e1; eb += 256) {
+    const int64_t me = eb + lane;
+    const bool ok = me < e1 && (!sub || sub[me] == sel);
+    const int32_t mj = ok ? idx[me] : 0;
+    const double mv = ok ? w[me] * mt[me] : 0.0;
+    const int cnt = (int)std::min<int64_t>(64, e1 - eb);
+    for (int u = 0; u < cnt; u += NG * 8) {
+      double y[8], v[8];
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int src = (u + s8 * NG + g) & 63;
+        const int j = __shfl(mj, src, 64);
+        v[s8] = __shfl(mv, src, 64);
+        y[s8] = (a < p && v[s8] != 0.0) ? Y[(int64_t)j * p + a] : 0.0;
+      }
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) acc = fma(v[s8], y[s8], acc);
+    }
   }
-  if (lane < p) Xout[o * p + lane] = acc;
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  red[wave * 64 + lane] = acc;
+  __syncthreads();
+  if (wave == 0 && g == 0 && a < p)
+    Xout[o * p + a] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
 }
 
 __global__ void gaussian_block_kernel(int64_t n, int p, uint64_t seed, double *__restrict__ Y) {
@@ -377,21 +415,27 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, i
 }
 
 // ---------------------------------------------------------------- weighted LS solves
-// One wave per output row o. RT = ceil((r+1)/16) MFMA tiles per side.
+// One workgroup (4 waves) per output row o; RT = ceil((r+1)/16) MFMA tiles per
+// side. Each wave takes every fourth chunk of 64 entries: the chunk's metadata
+// is loaded one entry per lane, then BATCH groups of four entries have their
+// rows of the fixed factor loaded together before their MFMAs. The four waves'
+// Gram tiles are summed in LDS and the r x r system is solved there.
 template <int RT>
-__global__ __launch_bounds__(64) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                      const double *__restrict__ w, const double *__restrict__ mt,
-                                                      const uint8_t *__restrict__ sub, int sel,
-                                                      const double *__restrict__ Q, int r, int64_t n_out,
-                                                      double *__restrict__ Xout) {
+__global__ __launch_bounds__(256) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                       const double *__restrict__ w, const double *__restrict__ mt,
+                                                       const uint8_t *__restrict__ sub, int sel,
+                                                       const double *__restrict__ Q, int r, int64_t n_out,
+                                                       double *__restrict__ Xout) {
   constexpr int D = RT * 16;
-  __shared__ double G[D * D];
+  constexpr int BATCH = RT == 3 ? 4 : 8;
+  __shared__ double Gw[4 * D * D];
   __shared__ double L[32 * 32];
   __shared__ double hv[32];
   const int64_t o = blockIdx.x;
   if (o >= n_out) return;
   const int t = threadIdx.x;
-  const int col = t & 15, ent = t >> 4;
+  const int wave = t >> 6, lt = t & 63;
+  const int col = lt & 15, ent = lt >> 4;
   v4d acc[RT][RT];
 #pragma unroll
   for (int a = 0; a < RT; ++a)
@@ -399,49 +443,63 @@ __global__ __launch_bounds__(64) void ls_solve_kernel(const int64_t *__restrict_
     for (int b = 0; b < RT; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
   const int64_t e0 = ptr[o], e1 = ptr[o + 1];
-  for (int64_t eb = e0; eb < e1; eb += 4) {
-    const int64_t e = eb + ent;
-    double we = 0.0, me = 0.0;
-    int64_t row = 0;
-    if (e < e1 && (!sub || sub[e] == sel)) {
-      we = w[e];
-      me = mt[e];
-      row = idx[e];
+  for (int64_t eb = e0 + 64 * wave; eb < e1; eb += 256) {
+    const int64_t me = eb + lt;
+    const bool ok = me < e1 && (!sub || sub[me] == sel);
+    const int32_t mrow = ok ? idx[me] : 0;
+    const double mw = ok ? w[me] : 0.0;
+    const double mm = ok ? mt[me] : 0.0;
+    const int nsteps = (int)std::min<int64_t>(16, (e1 - eb + 3) / 4);
+    for (int s0 = 0; s0 < nsteps; s0 += BATCH) {
+      double af[BATCH][RT], bf[BATCH][RT];
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q) {
+        const int src = (4 * (s0 + q) + ent) & 63;
+        const int32_t row = __shfl(mrow, src, 64);
+        const double we = __shfl(mw, src, 64);
+        const double me_ = __shfl(mm, src, 64);
+        const bool live = s0 + q < nsteps && we != 0.0;
+#pragma unroll
+        for (int tt = 0; tt < RT; ++tt) {
+          const int a = tt * 16 + col;
+          double x = 0.0;
+          if (live) x = a < r ? Q[(int64_t)row * r + a] : (a == r ? me_ : 0.0);
+          bf[q][tt] = x;
+          af[q][tt] = a < r ? we * x : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q)
+#pragma unroll
+        for (int ta = 0; ta < RT; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < RT; ++tb)
+            acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q][ta], bf[q][tb], acc[ta][tb], 0, 0, 0);
     }
-    double af[RT], bf[RT];
-#pragma unroll
-    for (int tt = 0; tt < RT; ++tt) {
-      const int a = tt * 16 + col;
-      double x = 0.0;
-      if (we != 0.0) x = a < r ? Q[row * r + a] : (a == r ? me : 0.0);
-      bf[tt] = x;
-      af[tt] = a < r ? we * x : 0.0;
-    }
-#pragma unroll
-    for (int ta = 0; ta < RT; ++ta)
-#pragma unroll
-      for (int tb = 0; tb < RT; ++tb) acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ta], bf[tb], acc[ta][tb], 0, 0, 0);
   }
   // v_mfma_f64_16x16x4f64 leaves D[4*j + t/16][t%16] in register j of lane t
+  double *Gme = Gw + wave * D * D;
 #pragma unroll
   for (int ta = 0; ta < RT; ++ta)
 #pragma unroll
     for (int tb = 0; tb < RT; ++tb)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) G[(ta * 16 + 4 * j + ent) * D + tb * 16 + col] = acc[ta][tb][j];
+      for (int j = 0; j < 4; ++j) Gme[(ta * 16 + 4 * j + ent) * D + tb * 16 + col] = acc[ta][tb][j];
   __syncthreads();
+  for (int e = t; e < D * D; e += 256) Gw[e] = ((Gw[e] + Gw[D * D + e]) + Gw[2 * D * D + e]) + Gw[3 * D * D + e];
+  __syncthreads();
+  const double *G = Gw;
 
   double mx = 0.0, tr = 0.0;
   for (int a = 0; a < r; ++a) {
     mx = fmax(mx, G[a * D + a]);
     tr += G[a * D + a];
   }
-  double x_out = 0.0;
   bool solved = false;
   for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
     const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
     const double tol = 1e-12 * (mx + shift);
-    for (int e = t; e < r * r; e += 64) {
+    for (int e = t; e < r * r; e += 256) {
       const int i = e / r, c = e % r;
       L[i * 32 + c] = G[i * D + c] + ((i == c) ? shift : 0.0);
     }
@@ -454,10 +512,10 @@ __global__ __launch_bounds__(64) void ls_solve_kernel(const int64_t *__restrict_
       const double d = sqrt(piv);
       __syncthreads();
       if (t == 0) L[j * 32 + j] = d;
-      for (int i = j + 1 + t; i < r; i += 64) L[i * 32 + j] /= d;
+      for (int i = j + 1 + t; i < r; i += 256) L[i * 32 + j] /= d;
       __syncthreads();
       const int m = r - j - 1;
-      for (int e = t; e < m * m; e += 64) {
+      for (int e = t; e < m * m; e += 256) {
         const int i = j + 1 + e / m, c = j + 1 + e % m;
         if (c <= i) L[i * 32 + c] -= L[i * 32 + j] * L[c * 32 + j];
       }
@@ -473,7 +531,7 @@ __global__ __launch_bounds__(64) void ls_solve_kernel(const int64_t *__restrict_
       const double yi = hv[i] / L[i * 32 + i];
       __syncthreads();
       if (t == 0) hv[i] = yi;
-      for (int k = i + 1 + t; k < r; k += 64) hv[k] -= L[k * 32 + i] * yi;
+      for (int k = i + 1 + t; k < r; k += 256) hv[k] -= L[k * 32 + i] * yi;
     }
     // backward: L^T x = y
     for (int i = r - 1; i >= 0; --i) {
@@ -481,15 +539,12 @@ __global__ __launch_bounds__(64) void ls_solve_kernel(const int64_t *__restrict_
       const double xi = hv[i] / L[i * 32 + i];
       __syncthreads();
       if (t == 0) hv[i] = xi;
-      for (int k = t; k < i; k += 64) hv[k] -= L[i * 32 + k] * xi;
+      for (int k = t; k < i; k += 256) hv[k] -= L[i * 32 + k] * xi;
     }
     __syncthreads();
     solved = true;
   }
-  if (t < r) {
-    x_out = solved ? hv[t] : 0.0;
-    Xout[o * r + t] = x_out;
-  }
+  if (t < r) Xout[o * r + t] = solved ? hv[t] : 0.0;
 }
 
 // ---------------------------------------------------------------- host helpers
@@ -544,32 +599,52 @@ size_t carve_bytes(int64_t n1, int64_t n2, int p, int r) {
   return s;
 }
 
-void gram(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
-  const int nblk = (int)std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + 255) / 256));
+int gram(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
+  const int nblk = (int)std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + 63) / 64));
   const int64_t rpb = (n + nblk - 1) / nblk;
   hipLaunchKernelGGL(gram_partial_kernel, dim3(nblk), dim3(256), 0, st, X, n, p, rpb, w.part);
+  return nblk;
+}
+
+// G = X^T X into w.G (for the small eigenproblems).
+void gram_full(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
+  const int nblk = gram(w, X, n, p, st);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(cdiv(p * p, 256)), dim3(256), 0, st, w.part, nblk, p, w.G);
 }
 
 void apply(const double *X, int64_t n, int pin, const double *M, int pout, double *Xout, hipStream_t st) {
-  hipLaunchKernelGGL(apply_kernel, dim3(std::min<unsigned>(cdiv(n * pout, 256), 4096)), dim3(256), 0, st, X, n, pin,
-                     M, pout, Xout);
+  hipLaunchKernelGGL(apply_kernel, dim3(cdiv(n, 4)), dim3(256), 0, st, X, n, pin, M, pout, Xout);
 }
 
-// X (n x p) <- orthonormal basis of its span (CholeskyQR2); uses w.T1 as scratch.
+// X (n x p) <- X L^-T for X^T X (+ a tiny shift) = L L^T: one CholeskyQR pass,
+// span preserved; twice gives orthonormal columns to working precision.
+void cholqr_pass(const Ws &w, const double *X, int64_t n, int p, double shift_rel, double *Xout, hipStream_t st) {
+  const int nblk = gram(w, X, n, p, st);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
+  apply(X, n, p, w.M, p, Xout, st);
+}
+
+// X (n x p) <- orthonormal basis of its span (CholeskyQR2, in place).
 void orth(const Ws &w, double *X, int64_t n, int p, hipStream_t st) {
-  gram(w, X, n, p, st);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, w.G, p, 1e-14, w.M, (double *)nullptr);
-  apply(X, n, p, w.M, p, w.T1, st);
-  gram(w, w.T1, n, p, st);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), 0, st, w.G, p, 0.0, w.M, (double *)nullptr);
-  apply(w.T1, n, p, w.M, p, X, st);
+  cholqr_pass(w, X, n, p, 1e-14, X, st);
+  cholqr_pass(w, X, n, p, 0.0, X, st);
+}
+
+// One shifted CholeskyQR pass: the span is kept and the columns come out
+// orthonormal up to O(eps cond(X)^2), enough to condition the next solve.
+void orth1(const Ws &w, double *X, int64_t n, int p, hipStream_t st) {
+  cholqr_pass(w, X, n, p, 1e-14, X, st);
 }
 
 void spmm(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
           const double *Y, int p, int64_t n_out, double *Xout, hipStream_t st) {
-  hipLaunchKernelGGL(spmm_kernel, dim3(cdiv(n_out, 4)), dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out,
-                     Xout);
+  const dim3 grid((unsigned)std::max<int64_t>(1, n_out)), blk(256);
+  if (p <= 16)
+    hipLaunchKernelGGL(spmm_kernel<16>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Xout);
+  else if (p <= 32)
+    hipLaunchKernelGGL(spmm_kernel<32>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Xout);
+  else
+    hipLaunchKernelGGL(spmm_kernel<64>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Xout);
 }
 
 void ls_solve(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
@@ -577,18 +652,18 @@ void ls_solve(const int64_t *ptr, const int32_t *idx, const double *wt, const do
   const int rt = (r + 1 + 15) / 16;
   const dim3 grid((unsigned)std::max<int64_t>(1, n_out));
   if (rt == 1)
-    hipLaunchKernelGGL(ls_solve_kernel<1>, grid, dim3(64), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    hipLaunchKernelGGL(ls_solve_kernel<1>, grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
   else if (rt == 2)
-    hipLaunchKernelGGL(ls_solve_kernel<2>, grid, dim3(64), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    hipLaunchKernelGGL(ls_solve_kernel<2>, grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
   else
-    hipLaunchKernelGGL(ls_solve_kernel<3>, grid, dim3(64), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    hipLaunchKernelGGL(ls_solve_kernel<3>, grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
 }
 
 // U (n1 x r), V (n2 x r, orthonormal columns) -> canonical Uc, sigma, Vc
 // (U V^T = Uc diag(sigma) Vc^T). Uc written to Uout, Vc to Vout.
 void canonical(const Ws &w, const double *U, int64_t n1, const double *V, int64_t n2, int r, double *Uout,
                double *Vout, double *sigma, hipStream_t st) {
-  gram(w, U, n1, r, st);
+  gram_full(w, U, n1, r, st);
   hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(64), 0, st, w.G, r, w.W, w.lam);
   hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, r, r, w.Mu, w.Mv, sigma);
   apply(U, n1, r, w.Mu, r, Uout, st);
@@ -608,7 +683,7 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   const int64_t n1 = om.n1, n2 = om.n2;
   const int r = prm.r, T = prm.T;
   const int p = std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample)));
-  const int iters = prm.init_iters > 0 ? prm.init_iters : 12;
+  const int iters = prm.init_iters > 0 ? prm.init_iters : 6;
   const bool split = prm.omega_mode == SMP_OMEGA_SPLIT;
   Ws w = carve_ws(wsbase, n1, n2, p, r);
   const uint8_t *scsr = split ? om.sub_csr : nullptr;
@@ -619,16 +694,17 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   // ---- init: subspace iteration on R = w .* P_Omega0(M~)
   hipLaunchKernelGGL(gaussian_block_kernel, dim3(cdiv(n2 * ((p + 3) / 4), 256)), dim3(256), 0, st, n2, p, prm.seed,
                      w.Y);
-  orth(w, w.Y, n2, p, st);
+  orth1(w, w.Y, n2, p, st);
   for (int it = 0; it < iters; ++it) {
     spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
-    orth(w, w.X, n1, p, st);
+    orth1(w, w.X, n1, p, st);
     spmm(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 0, w.X, p, n2, w.Y, st);
-    orth(w, w.Y, n2, p, st);
+    if (it + 1 < iters) orth1(w, w.Y, n2, p, st);
   }
+  orth(w, w.Y, n2, p, st);
   spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
   // Rayleigh-Ritz: X = R Y; X^T X = W diag(lam) W^T; U0 = X W_r lam^-1/2, V0 = Y W_r
-  gram(w, w.X, n1, p, st);
+  gram_full(w, w.X, n1, p, st);
   hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(64), 0, st, w.G, p, w.W, w.lam);
   hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, p, r, w.Mu, w.Mv, w.sig);
   apply(w.X, n1, p, w.Mu, r, w.U, st);
@@ -639,9 +715,9 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
     hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
   } else {
     for (int t = 0; t < T; ++t) {
-      orth(w, w.U, n1, r, st);                                          // Q_U
+      orth1(w, w.U, n1, r, st);                                         // Q_U
       ls_solve(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 2 * t + 1, w.U, r, n2, w.V, st);
-      orth(w, w.V, n2, r, st);                                          // Q_V
+      if (t + 1 < T) orth1(w, w.V, n2, r, st); else orth(w, w.V, n2, r, st);   // Q_V
       ls_solve(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 2 * t + 2, w.V, r, n1, w.U, st);
     }
   }

