@@ -37,7 +37,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the CPU-oracle sample (0: all d rows)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 2^30 bytes (the reference dispatch for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def recorded_traffic():
+    """HBM bytes per sketch launch from the committed rocprofv3 counter runs,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sketch_c2_fp32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sha256"] else None
 
 
 def pct(xs, q):
@@ -132,7 +149,8 @@ def main():
                                "FP64 WAltMin", "d": c["d"], "n1": c["n1"], "n2": c["n2"], "k": c["k"],
                    "r": c["r"], "T": c["T"], "m": round(p.m, 3), "input_gb": round(in_bytes / 1e9, 3)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+                     "traffic": recorded_traffic(),
                      "kernel": "sketch_kernel (FP32 v_mfma_f32_16x16x4f32)",
                      "kernel_ms": round(sk_ms, 4), "flops_per_launch": flops},
         "solves_per_s": round(1e3 / ms_step, 3),
@@ -141,6 +159,14 @@ def main():
         "sketch_pass_gbps": round(in_bytes / (sk_ms / 1e3) / 1e9, 2),
         "sketch_pass_hbm_frac": round(in_bytes / (sk_ms / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, c, p.m, seed, args.cpu_rows)
     print(json.dumps(out), flush=True)
