@@ -6,11 +6,14 @@ A step is one smp_solve (Alg. 1 end to end: sketch pass, sampling, rescaled-JL
 estimates, WAltMin, canonical form) over the dense FP32 workload
 d = 200,000, n1 = n2 = 2,000, k = 400, r = 10, T = 10, m = 4 n r ln n
 (latent rank 10, noise 0.1, column scaling (j+1)^-0.5), with A and B already
-resident in HBM. `value` is input bytes consumed per second, 4 d (n1+n2) / t.
+resident in HBM. `value` is input bytes consumed per second, 4 d (n1+n2) / t,
+of the BF16-sketch solve (sketch GEMM operands rounded to bfloat16, FP32
+accumulation, FP64 WAltMin); the same solve with the FP32 sketch is timed
+beside it ("fp32"), and each leg's spectral error is reported.
 
-Also reported: the dominant kernel's roofline (the sketch pass, FP32 matrix
-cores, timed with HIP events on the library's stream), per-stage times,
-solves/s with p50/p99 latency, and the FP64 CPU oracle timed on the host.
+Also reported: the dominant kernel's roofline (the sketch pass, timed with HIP
+events on the library's stream), per-stage times, solves/s with p50/p99
+latency, and the FP64 CPU oracle timed on the host.
 """
 
 import argparse
@@ -43,11 +46,12 @@ def parse():
     return ap.parse_args()
 
 
-def recorded_traffic():
-    """HBM bytes per sketch launch from the committed rocprofv3 counter runs,
-    or None when the kernel sources changed since the counters were taken."""
+def recorded_traffic(name):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    runs (profiles/<name>.json), or None when the kernel's sources changed
+    since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sketch_c2_fp32_traffic.json")
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -86,6 +90,60 @@ def cpu_baseline(A, B, c, m, seed, rows):
                       f"({gbytes:.2f} GB of FP32 input), {dt:.1f} s"}
 
 
+def spectral_error(A, B, U, s, V, iters=60):
+    """||A^T B - U diag(s) V^T||_2 / ||A^T B||_2 by power iteration in FP64
+    on the device (evaluation only, outside the timed region)."""
+    import torch
+    M = A.double().T @ B.double()
+    E = M - (U * s[None, :]) @ V.T
+
+    def norm2(X):
+        g = torch.Generator(device=X.device).manual_seed(7)
+        v = torch.randn(X.shape[1], dtype=torch.float64, device=X.device, generator=g)
+        for _ in range(iters):
+            v = X.T @ (X @ v)
+            v /= torch.linalg.vector_norm(v)
+        return torch.linalg.vector_norm(X @ v).item()
+
+    return norm2(E) / norm2(M)
+
+
+def run_leg(ctx, api, A, B, c, seed, prec, steps, warmup):
+    import torch
+    dev = A.device
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed, prec=prec)
+    U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=dev)
+    V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=dev)
+    s = torch.empty(c["r"], dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        ctx.smp_solve(p, A, B, U, V, s)
+    torch.cuda.synchronize()
+    lat, stages = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        ctx.smp_solve(p, A, B, U, V, s)          # synchronises at its end
+        lat.append((time.perf_counter() - ts) * 1e3)
+        stages.append(ctx.smp_stage_times())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / steps * 1e3
+    in_bytes = 4.0 * c["d"] * (c["n1"] + c["n2"])
+    avg = {k: sum(st[k] for st in stages) / len(stages) for k in stages[0]}
+    return dict(p=p, ms_step=ms_step, in_bytes=in_bytes, avg=avg, lat=lat,
+                err=spectral_error(A, B, U, s, V))
+
+
+def leg_summary(leg):
+    sk = leg["avg"]["sketch"]
+    return {"ms_per_step": round(leg["ms_step"], 4), "solves_per_s": round(1e3 / leg["ms_step"], 3),
+            "latency_ms": {"p50": round(pct(leg["lat"], 50), 4), "p99": round(pct(leg["lat"], 99), 4)},
+            "stages_ms": {k: round(v, 4) for k, v in leg["avg"].items()},
+            "sketch_pass_gbps": round(leg["in_bytes"] / (sk / 1e3) / 1e9, 2),
+            "sketch_pass_hbm_frac": round(leg["in_bytes"] / (sk / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
+            "spectral_error": leg["err"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -104,33 +162,19 @@ def main():
     torch.cuda.synchronize()
     ctx = api.Context(0)
     ctx.smp_set_timing(True)
-    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed)
-    U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=dev)
-    V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=dev)
-    s = torch.empty(c["r"], dtype=torch.float64, device=dev)
 
-    for _ in range(args.warmup):
-        ctx.smp_solve(p, A, B, U, V, s)
-    torch.cuda.synchronize()
+    fp32 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_FP32, args.steps, args.warmup)
+    bf16 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_BF16, args.steps, args.warmup)
 
-    lat, stages = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        ctx.smp_solve(p, A, B, U, V, s)          # synchronises at its end
-        lat.append((time.perf_counter() - ts) * 1e3)
-        stages.append(ctx.smp_stage_times())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    ms_step = wall / args.steps * 1e3
-    in_bytes = 4.0 * c["d"] * (c["n1"] + c["n2"])
+    in_bytes = bf16["in_bytes"]
+    ms_step = bf16["ms_step"]
     value = in_bytes / (ms_step / 1e3) / 1e9
-    avg = {k: sum(st[k] for st in stages) / len(stages) for k in stages[0]}
-    sk_ms = avg["sketch"]
+    sk_bf16 = bf16["avg"]["sketch"]
+    sk_fp32 = fp32["avg"]["sketch"]
     flops = (2.0 * c["k"] + 4.0) * c["d"] * (c["n1"] + c["n2"])
-    achieved = flops / (sk_ms / 1e3) / 1e12
+    fp32_tflops = flops / (sk_fp32 / 1e3) / 1e12
+    hbm_gbps = in_bytes / (sk_bf16 / 1e3) / 1e9
+    p = bf16["p"]
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -142,22 +186,29 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "SMP-PCA end to end, dense latent-rank-10 A and B (noise 0.1, column scale "
-                               "(j+1)^-0.5), d=200000, n1=n2=2000, k=400, r=10, T=10, m=4nr ln n, FP32 sketch, "
-                               "FP64 WAltMin", "d": c["d"], "n1": c["n1"], "n2": c["n2"], "k": c["k"],
+                               "(j+1)^-0.5), d=200000, n1=n2=2000, k=400, r=10, T=10, m=4nr ln n; BF16 sketch "
+                               "GEMM (FP32 accumulate, FP32 compensated norms), FP64 sampling weights, "
+                               "estimates and WAltMin", "d": c["d"], "n1": c["n1"], "n2": c["n2"], "k": c["k"],
                    "r": c["r"], "T": c["T"], "m": round(p.m, 3), "input_gb": round(in_bytes / 1e9, 3)},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
-                     "traffic": recorded_traffic(),
-                     "kernel": "sketch_kernel (FP32 v_mfma_f32_16x16x4f32)",
-                     "kernel_ms": round(sk_ms, 4), "flops_per_launch": flops},
+        "roofline": {"bound": "hbm", "achieved": round(hbm_gbps, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(hbm_gbps / PEAK_HBM_GBPS, 4),
+                     "traffic": recorded_traffic("sketch_bf16_c2_traffic"),
+                     "kernel": "sketch_bf16_kernel (v_mfma_f32_16x16x32_bf16), main and tail launch",
+                     "kernel_ms": round(sk_bf16, 4), "bytes_per_launch": in_bytes},
         "solves_per_s": round(1e3 / ms_step, 3),
-        "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
-        "stages_ms": {k: round(v, 4) for k, v in avg.items()},
-        "sketch_pass_gbps": round(in_bytes / (sk_ms / 1e3) / 1e9, 2),
-        "sketch_pass_hbm_frac": round(in_bytes / (sk_ms / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
+        "latency_ms": {"p50": round(pct(bf16["lat"], 50), 4), "p99": round(pct(bf16["lat"], 99), 4)},
+        "spectral_error": bf16["err"],
+        "bf16": leg_summary(bf16),
+        "fp32": dict(leg_summary(fp32), roofline={
+            "bound": "mfma", "achieved": round(fp32_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(fp32_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+            "traffic": recorded_traffic("sketch_fp32_c2_traffic"),
+            "kernel": "sketch_kernel (v_mfma_f32_16x16x4f32)", "kernel_ms": round(sk_fp32, 4),
+            "flops_per_launch": flops}),
+        "bf16_vs_fp32_solves": round(fp32["ms_step"] / bf16["ms_step"], 3),
     }
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)

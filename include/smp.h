@@ -65,7 +65,8 @@ typedef enum smp_status {
 
 typedef enum smp_precision {
   SMP_PREC_FP32 = 0,        /* sketch GEMM operands FP32 (v_mfma_f32_16x16x4_f32) */
-  SMP_PREC_BF16 = 1         /* operands rounded to BF16, FP32 accumulate */
+  SMP_PREC_BF16 = 1         /* Pi and data rounded to bfloat16 (nearest even), FP32 accumulate
+                               (v_mfma_f32_16x16x32_bf16); the norms use the unrounded data */
 } smp_precision;
 
 typedef enum smp_omega_mode {

@@ -82,3 +82,42 @@ def sketch_with_pi(Pi, A, B):
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     return Pi @ A, Pi @ B, (A * A).sum(axis=0), (B * B).sum(axis=0)
+
+
+def sketch_lowp(A, B, seed, k, fmt, chunk=8192):
+    """The pass with the GEMM operands in a narrow format (no precision is
+    fixed by the paper; Alg. 1 step 2 forms Pi A and Pi B). Definition:
+    At = (1/sqrt(k)) R(Z) R(A), Bt = (1/sqrt(k)) R(Z) R(B) with R the rounding
+    of every entry to `fmt` (``oracle.rounding``) and the product exact (FP64
+    here). The squared column norms are those of the unrounded data.
+    fmt: "bf16". Same return convention as ``sketch``."""
+    from .rounding import round_bf16
+    if fmt != "bf16":
+        raise ValueError(f"unknown format {fmt!r}")
+    rnd = round_bf16
+    A = np.asarray(A)
+    d, n1 = A.shape
+    same = B is None
+    if not same:
+        B = np.asarray(B)
+        assert B.shape[0] == d
+    n2 = n1 if same else B.shape[1]
+    At = np.zeros((k, n1))
+    Bt = None if same else np.zeros((k, n2))
+    na2 = np.zeros(n1)
+    nb2 = None if same else np.zeros(n2)
+    for l0 in range(0, d, chunk):
+        l1 = min(d, l0 + chunk)
+        Z = rnd(gaussian_block(seed, k, l0, l1))
+        a = np.asarray(A[l0:l1], dtype=np.float64)
+        At += Z @ rnd(a)
+        na2 += np.einsum("li,li->i", a, a)
+        if not same:
+            b = np.asarray(B[l0:l1], dtype=np.float64)
+            Bt += Z @ rnd(b)
+            nb2 += np.einsum("li,li->i", b, b)
+    At /= np.sqrt(float(k))
+    if same:
+        return At, At, na2, na2
+    Bt /= np.sqrt(float(k))
+    return At, Bt, na2, nb2

@@ -20,8 +20,10 @@ def default_m(n1, n2, r):
     return 4.0 * n * r * math.log(n)
 
 
-def smp_pca(A, B, r, k, m, T, seed, split=False):
+def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None):
     """Run Alg. 1. A: d x n1, B: d x n2 or None (A = B, Section 3 Remark 3).
+    sketch_fmt: None for the FP64 pass, or a narrow format ("bf16") whose
+    rounded operands form the sketches (``oracle.sketch.sketch_lowp``).
     Returns a dict with the output factors and every intermediate:
       At, Bt, na2, nb2      sketches and squared column norms (step 2)
       omega                  oracle.sample.Omega (step 3)
@@ -29,7 +31,10 @@ def smp_pca(A, B, r, k, m, T, seed, split=False):
       U, V                   WAltMin output (step 5), U V^T the approximation
       Uc, sigma, Vc          canonical SVD form of U V^T
     """
-    At, Bt, na2, nb2 = _sketch.sketch(A, B, seed, k)
+    if sketch_fmt is None:
+        At, Bt, na2, nb2 = _sketch.sketch(A, B, seed, k)
+    else:
+        At, Bt, na2, nb2 = _sketch.sketch_lowp(A, B, seed, k, sketch_fmt)
     om = _sample.sample(na2, nb2, m, seed, T=T, split=split)
     mt = _estimate.estimate(At, Bt, na2, nb2, om.rows, om.cols)
     res = _waltmin.waltmin(om.n1, om.n2, om.rows, om.cols, om.w, mt, r, T, na2, om.FA,

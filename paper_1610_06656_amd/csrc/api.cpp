@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -50,7 +51,7 @@ std::string check(const smp_params *p) {
   if (p->T < 0 || p->T > 1000) return "T must be in [0, 1000]";
   if (p->T > 127 && p->omega_mode == SMP_OMEGA_SPLIT) return "SPLIT mode needs 2T+1 <= 255 subsets";
   if (!(p->m > 0.0) || !std::isfinite(p->m)) return "m must be a finite positive number";
-  if (p->prec != SMP_PREC_FP32) return "precision not available (only SMP_PREC_FP32)";
+  if (p->prec != SMP_PREC_FP32 && p->prec != SMP_PREC_BF16) return "unknown precision";
   if (p->omega_mode != SMP_OMEGA_REUSE && p->omega_mode != SMP_OMEGA_SPLIT) return "unknown omega_mode";
   if (p->init_iters < 0 || p->init_iters > 1000) return "init_iters must be in [0, 1000]";
   if (p->reserved != 0) return "reserved must be 0";
@@ -59,15 +60,34 @@ std::string check(const smp_params *p) {
   return "";
 }
 
-// Number of d-splits of the sketch pass: enough workgroups to fill the chip
-// (about two per CU) with at least 256 rows per split.
+// Number of d-splits S of the sketch pass. The kt * tiles * S workgroups run
+// in ceil(total / slots) rounds on the slots the device holds at once; the
+// S partial sketches are written once and read once by the reduction. S
+// minimises (streaming time with the last round's idle slots) + (partial
+// traffic), both relative to one perfectly balanced read of the input:
+//   cost(S) = rounds * slots / total + 2 S kpad / d,
+// with at least 256 rows per split.
 int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
   const int64_t tiles = (n1 + pl.ncol_tile - 1) / pl.ncol_tile + (n2 + pl.ncol_tile - 1) / pl.ncol_tile;
   const int64_t per = (int64_t)pl.kt * tiles;
-  int64_t S = (512 + per - 1) / per;
-  S = std::min<int64_t>(S, std::max<int64_t>(1, d / 256));
-  S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
-  return (int)S;
+  const int64_t slots = smp::sketch_slots(pl);
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(256, d / std::max(256, 2 * pl.kc)));
+  if (const char *e = getenv("SMP_SKETCH_SPLITS")) {   // tuning override
+    const long v = strtol(e, nullptr, 10);
+    if (v >= 1) return (int)std::min<int64_t>(v, smax);
+  }
+  int best = 1;
+  double best_cost = 1e300;
+  for (int64_t S = 1; S <= smax; ++S) {
+    const int64_t total = per * S;
+    const int64_t rounds = (total + slots - 1) / slots;
+    const double cost = (double)(rounds * slots) / (double)total + 2.0 * (double)S * pl.kpad / (double)d;
+    if (cost < best_cost - 1e-12) {
+      best_cost = cost;
+      best = (int)S;
+    }
+  }
+  return best;
 }
 
 smp_status ensure(smp_ctx *ctx, Buf &b, size_t bytes) {
@@ -212,11 +232,12 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes) {
   const std::string m = check(p);
   if (!m.empty()) return fail(nullptr, SMP_ERR_INVALID_ARG, m);
   if (!bytes) return fail(nullptr, SMP_ERR_INVALID_ARG, "bytes is NULL");
-  const SketchPlan pl = smp::sketch_plan(p->k);
+  const SketchPlan pl = smp::sketch_plan(p->k, p->prec);
   const int S = choose_splits(pl, p->d, p->n1, p->n2);
   const int64_t nt = p->n1 + p->n2, k = p->k;
   size_t s = 0;
-  s += al((size_t)S * nt * pl.kpad * 4) + al((size_t)S * nt * 8);        // sketch partials
+  const int slots = smp::sketch_slots_total(pl, S);
+  s += al((size_t)slots * nt * pl.kpad * 4) + al((size_t)slots * nt * 8);   // sketch partials
   s += al(nt * k * 4) + al(nt * 4);                                       // sketches + norms
   s += al(64) + al(nt * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);   // sampling
   const double nnz = std::min<double>((double)p->n1 * (double)p->n2, p->m + 6.0 * std::sqrt(p->m) + 64.0);
@@ -246,12 +267,13 @@ smp_status smp_sketch_begin(smp_ctx *ctx, const smp_params *p, smp_sketch_state 
   if (!s) return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "host allocation failed");
   s->ctx = ctx;
   s->p = *p;
-  s->plan = smp::sketch_plan(p->k);
+  s->plan = smp::sketch_plan(p->k, p->prec);
   s->S = choose_splits(s->plan, p->d, p->n1, p->n2);
   const int64_t n2 = (p->flags & SMP_B_IS_A) ? 0 : p->n2;
   const int64_t nt = p->n1 + n2;
-  const size_t pb = (size_t)s->S * nt * s->plan.kpad * sizeof(float);
-  const size_t nb = (size_t)s->S * nt * sizeof(double);
+  const int slots = smp::sketch_slots_total(s->plan, s->S);
+  const size_t pb = (size_t)slots * nt * s->plan.kpad * sizeof(float);
+  const size_t nb = (size_t)slots * nt * sizeof(double);
   if (hipMalloc((void **)&s->part, pb) != hipSuccess || hipMalloc((void **)&s->npart, nb) != hipSuccess) {
     hipGetLastError();
     if (s->part) hipFree(s->part);
@@ -276,7 +298,7 @@ smp_status smp_sketch_push(smp_ctx *ctx, smp_sketch_state *st, const float *A_ro
   if (!A_rows || lda < p.n1) return fail(ctx, SMP_ERR_INVALID_ARG, "A is NULL or lda < n1");
   if (!same && (!B_rows || ldb < p.n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
   SMP_HIP(ctx, smp::sketch_push(st->plan, A_rows, lda, p.n1, same ? nullptr : B_rows, ldb, same ? 0 : p.n2, row0,
-                                nrows, p.k, p.seed, st->S, st->part, st->npart, ctx->stream));
+                                nrows, p.k, p.seed, st->S, true, st->part, st->npart, ctx->stream));
   return SMP_OK;
 }
 
@@ -287,7 +309,8 @@ smp_status smp_sketch_end(smp_ctx *ctx, smp_sketch_state *st, float *At, float *
   if (!At || !na2) return fail(ctx, SMP_ERR_INVALID_ARG, "At or na2 is NULL");
   if (!same && (!Bt || !nb2)) return fail(ctx, SMP_ERR_INVALID_ARG, "Bt or nb2 is NULL");
   const int64_t n2 = same ? 0 : p.n2;
-  SMP_HIP(ctx, smp::sketch_finish(st->plan, st->part, st->npart, st->S, p.n1, n2, p.k, At, same ? nullptr : Bt, na2,
+  SMP_HIP(ctx, smp::sketch_finish(st->plan, st->part, st->npart, smp::sketch_slots_total(st->plan, st->S), p.n1, n2,
+                                  p.k, At, same ? nullptr : Bt, na2,
                                   same ? nullptr : nb2, ctx->stream));
   if (same) {
     if (Bt && Bt != At)
@@ -317,24 +340,24 @@ smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t
   if (!same && (!B || ldb < p->n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
   if (!At || !na2 || (!same && (!Bt || !nb2))) return fail(ctx, SMP_ERR_INVALID_ARG, "output pointer is NULL");
   // the one-shot pass keeps its partials in the context's workspace
-  const SketchPlan pl = smp::sketch_plan(p->k);
+  const SketchPlan pl = smp::sketch_plan(p->k, p->prec);
   const int S = choose_splits(pl, p->d, p->n1, p->n2);
   const int64_t n2 = same ? 0 : p->n2;
   const int64_t nt = p->n1 + n2;
-  const size_t pb = al((size_t)S * nt * pl.kpad * 4), nb = al((size_t)S * nt * 8);
+  const int slots = smp::sketch_slots_total(pl, S);
+  const size_t pb = al((size_t)slots * nt * pl.kpad * 4), nb = al((size_t)slots * nt * 8);
   smp_ctx_bufs &b = bufs(ctx);
   smp_status s = ensure(ctx, b.sketch, pb + nb);
   if (s != SMP_OK) return s;
   float *part = static_cast<float *>(b.sketch.p);
   double *npart = reinterpret_cast<double *>(static_cast<char *>(b.sketch.p) + pb);
   for (bool &r : ctx->recorded) r = false;
-  SMP_HIP(ctx, hipMemsetAsync(b.sketch.p, 0, pb + nb, ctx->stream));
   mark(ctx, kStSketch, false);
-  SMP_HIP(ctx, smp::sketch_push(pl, A, lda, p->n1, same ? nullptr : B, ldb, n2, 0, p->d, p->k, p->seed, S, part,
-                                npart, ctx->stream));
+  SMP_HIP(ctx, smp::sketch_push(pl, A, lda, p->n1, same ? nullptr : B, ldb, n2, 0, p->d, p->k, p->seed, S, false,
+                                part, npart, ctx->stream));
   mark(ctx, kStSketch, true);
   mark(ctx, kStFinish, false);
-  SMP_HIP(ctx, smp::sketch_finish(pl, part, npart, S, p->n1, n2, p->k, At, same ? nullptr : Bt, na2,
+  SMP_HIP(ctx, smp::sketch_finish(pl, part, npart, slots, p->n1, n2, p->k, At, same ? nullptr : Bt, na2,
                                   same ? nullptr : nb2, ctx->stream));
   mark(ctx, kStFinish, true);
   if (same) {

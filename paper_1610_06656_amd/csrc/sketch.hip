@@ -2,20 +2,21 @@
 //   A~ = Pi A, B~ = Pi B (Pi k x d, i.i.d. N(0, 1/k)) and ||A_i||^2, ||B_j||^2,
 // as one streaming split-K GEMM on the FP32 matrix cores of gfx950.
 //
-// Work decomposition. A workgroup (4 waves) owns
-//   * a tile of 64*NV data columns of A or B (each lane holds NV adjacent
+// Work decomposition. A workgroup of W waves owns
+//   * a tile of 16*W*NV data columns of A or B (each lane holds NV adjacent
 //     columns of one row, loaded with one vector load),
-//   * a chunk of MT*16 sketch rows (all of k when k <= 400 with NV = 2),
+//   * a chunk of MT*16 sketch rows (k = 400 runs as two chunks of 13 m-tiles),
 //   * one of S contiguous row ranges of the d rows (split-K).
-// It streams its rows in chunks of 16. For every chunk the workgroup
-// regenerates the MT*16 x 16 block of Pi it needs from the Philox counter
-// spec into LDS (Pi is never stored in HBM), and feeds the data rows straight
-// from HBM into v_mfma_f32_16x16x4_f32 as the B operand: lane (q, ph) of a
-// wave supplies row ph of each 4-row K step for its NV columns, so n-tile v of
-// the MFMA sees column (base + q*NV + v). The squared column norms are
-// accumulated from the same registers with per-lane compensated (Kahan) FP32
-// sums. The S row ranges write FP32 partial sketches and FP64 partial norms;
-// sketch_finish reduces them in a fixed order (deterministic, no atomics).
+// It streams its rows in chunks of KC. For every chunk the workgroup
+// regenerates the MT*16 x KC block of Pi it needs from the Philox counter
+// spec into LDS (Pi is never stored in HBM; rows past the range end get zero
+// Pi entries) and feeds the data rows straight from HBM into
+// v_mfma_f32_16x16x4_f32 as the B operand: lane (q, ph) of a wave supplies row
+// ph of each 4-row K step for its NV columns, so n-tile v of the MFMA sees
+// column (base + q*NV + v). The squared column norms are accumulated from the
+// same registers with per-lane compensated (Kahan) FP32 sums. The S row ranges
+// write FP32 partial sketches and FP64 partial norms; sketch_finish reduces
+// them in a fixed order (deterministic, no atomics).
 //
 // Workgroups that read the same data tile (same column tile and row range,
 // different sketch-row chunk) get consecutive logical ids placed on the same
@@ -25,70 +26,21 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "sketch_common.hpp"
 #include "smp_device.hpp"
 #include "smp_internal.hpp"
 
 namespace smp {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef float v2f __attribute__((ext_vector_type(2)));
-
 namespace {
-
-
-struct SkMat {
-  const float *X;
-  int64_t ld, n, col_base;
-  int ntiles, vec_ok;
-};
-
-struct SkArgs {
-  SkMat a, b;
-  int64_t row0, rows, rows_per_split, ntot;
-  int k, kpad, kt, mt_total, S;
-  uint64_t seed;
-  float *part;
-  double *npart;
-};
-
-// NV columns of one row into registers. FULL: the whole tile is inside the
-// matrix and vector loads are aligned, so the load is unconditional (the row
-// index is clamped into the row range and the value zeroed when it is out).
-template <int NV, bool FULL>
-__device__ __forceinline__ void load_row(const float *X, int64_t ld, int64_t n, int64_t row, int64_t row_last,
-                                         int64_t col, bool vec_ok, float (&out)[NV]) {
-  const bool row_ok = row <= row_last;
-  if constexpr (FULL) {
-    const float *p = X + (row_ok ? row : row_last) * ld + col;
-    if constexpr (NV == 2) {
-      const v2f t = __builtin_nontemporal_load(reinterpret_cast<const v2f *>(p));
-      out[0] = t[0]; out[1] = t[1];
-    } else {
-#pragma unroll
-      for (int h = 0; h < NV / 4; ++h) {
-        const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(p) + h);
-        out[4 * h + 0] = t[0]; out[4 * h + 1] = t[1]; out[4 * h + 2] = t[2]; out[4 * h + 3] = t[3];
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = row_ok ? out[v] : 0.0f;
-  } else {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = 0.0f;
-    if (!row_ok || col >= n) return;
-    const float *p = X + row * ld + col;
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-      if (col + v < n) out[v] = p[v];
-  }
-}
 
 // Pi block for sketch rows [c0, c0 + 16 MT) and data rows [lg, lg + KC) into
 // LDS as z (unscaled N(0,1)), layout P[row][c]. Every thread makes CPT Philox
 // calls (4 sketch rows each); the calls past MT*64 only pad the trip count and
-// land in a scratch slot. Rows c >= k are zero.
+// land in a scratch slot. Sketch rows c >= k and data rows past the first
+// `valid` of the block are zero.
 template <int MT, int W, int KC>
-__device__ __forceinline__ void gen_pi(float *P, int tid, uint64_t seed, uint64_t lg, int c0, int k) {
+__device__ __forceinline__ void gen_pi(float *P, int tid, uint64_t seed, uint64_t lg, int64_t valid, int c0, int k) {
   constexpr int kThreads = 64 * W;
   constexpr int MR = MT * 16, PST = MR + 4;
   constexpr int NCALL = MT * 4 * KC;
@@ -100,32 +52,32 @@ __device__ __forceinline__ void gen_pi(float *P, int tid, uint64_t seed, uint64_
     const int cb = idx - lr * (MT * 4);
     const int c = c0 + cb * 4;
     float4 z = normals4(stream_call(seed, kTagPi, lg + (uint64_t)lr, (uint32_t)(c >> 2)));
-    z.x = c + 0 < k ? z.x : 0.f;
-    z.y = c + 1 < k ? z.y : 0.f;
-    z.z = c + 2 < k ? z.z : 0.f;
-    z.w = c + 3 < k ? z.w : 0.f;
+    const bool rv = lr < valid;
+    z.x = rv && c + 0 < k ? z.x : 0.f;
+    z.y = rv && c + 1 < k ? z.y : 0.f;
+    z.z = rv && c + 2 < k ? z.z : 0.f;
+    z.w = rv && c + 3 < k ? z.w : 0.f;
     const int slot = (NCALL % kThreads == 0 || idx < NCALL) ? lr * PST + cb * 4 : KC * PST + tid * 4;
     *reinterpret_cast<float4 *>(&P[slot]) = z;
   }
 }
 
 template <int MT, int NV, int W, int KC, bool FULL>
-__device__ __forceinline__ void sketch_loop(const SkArgs &g, const float *X, int64_t ld, int64_t n, bool vec_ok,
-                                            int64_t lbeg, int64_t lend, int64_t col, int c0, float *P0, float *P1,
-                                            v4f (&acc)[MT][NV], float (&ksum)[NV], float (&kcmp)[NV]) {
+__device__ __forceinline__ void sketch_loop(const SkArgs &g, const SkWork &w, int64_t col, int c0, float *P0,
+                                            float *P1, v4f (&acc)[MT][NV], float (&ksum)[NV], float (&kcmp)[NV]) {
   constexpr int MR = MT * 16, PST = MR + 4;
   constexpr int NST = KC / 4;   // MFMA K steps per chunk
   const int tid = threadIdx.x;
   const int lane = tid & 63, q = lane & 15, ph = lane >> 4;
-  const int64_t row_last = lend - 1;
+  const int64_t row_last = w.lend - 1;
 
   float xv[NST][NV];
 #pragma unroll
-  for (int st = 0; st < NST; ++st) load_row<NV, FULL>(X, ld, n, lbeg + 4 * st + ph, row_last, col, vec_ok, xv[st]);
-  gen_pi<MT, W, KC>(P0, tid, g.seed, (uint64_t)(g.row0 + lbeg), c0, g.k);
+  for (int st = 0; st < NST; ++st) sk_load_row<NV, FULL, true>(w.X, w.ld, w.n, w.lbeg + 4 * st + ph, row_last, col, xv[st]);
+  gen_pi<MT, W, KC>(P0, tid, g.seed, (uint64_t)(g.row0 + w.lbeg), w.lend - w.lbeg, c0, g.k);
 
   int buf = 0;
-  for (int64_t l = lbeg; l < lend; l += KC) {
+  for (int64_t l = w.lbeg; l < w.lend; l += KC) {
     __syncthreads();   // Pi of this chunk is complete; the other buffer is free
     float *Pc = buf ? P1 : P0;
     float *Pn = buf ? P0 : P1;
@@ -133,19 +85,15 @@ __device__ __forceinline__ void sketch_loop(const SkArgs &g, const float *X, int
     float xn[NST][NV];
 #pragma unroll
     for (int st = 0; st < NST; ++st)
-      load_row<NV, FULL>(X, ld, n, l + KC + 4 * st + ph, row_last, col, vec_ok, xn[st]);
-    gen_pi<MT, W, KC>(Pn, tid, g.seed, (uint64_t)(g.row0 + l + KC), c0, g.k);
+      sk_load_row<NV, FULL, true>(w.X, w.ld, w.n, l + KC + 4 * st + ph, row_last, col, xn[st]);
+    gen_pi<MT, W, KC>(Pn, tid, g.seed, (uint64_t)(g.row0 + l + KC), w.lend - (l + KC), c0, g.k);
 
 #pragma unroll
-    for (int st = 0; st < NST; ++st)
+    for (int st = 0; st < NST; ++st) {
+      const bool rv = l + 4 * st + ph <= row_last;   // rows past the split end re-read row_last
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const float x = xv[st][v];
-        const float y = x * x - kcmp[v];
-        const float t = ksum[v] + y;
-        kcmp[v] = (t - ksum[v]) - y;
-        ksum[v] = t;
-      }
+      for (int v = 0; v < NV; ++v) kahan_add(ksum[v], kcmp[v], rv ? xv[st][v] * xv[st][v] : 0.0f);
+    }
 #pragma unroll
     for (int st = 0; st < NST; ++st) {
 #pragma unroll
@@ -172,36 +120,14 @@ __global__ __launch_bounds__(64 * W) void sketch_kernel(SkArgs g) {
   constexpr int PBUF = KC * PST + kThreads * 4;   // one Pi block + a scratch slot per thread
   __shared__ __attribute__((aligned(16))) float P[2 * PBUF];
 
-  // ---- XCD-aware decode of the workgroup id (grid size is a multiple of 8)
-  const int nb = gridDim.x;
-  const int b = blockIdx.x;
-  const int logical = (b & 7) * (nb >> 3) + (b >> 3);
-  const int ntl = g.a.ntiles + g.b.ntiles;
-  const int nlog = g.kt * ntl * g.S;
-  if (logical >= nlog) return;
-  const int kc = logical % g.kt;
-  const int rest = logical / g.kt;
-  int tile = rest % ntl;
-  const int s = rest / ntl;
-  const bool isb = tile >= g.a.ntiles;
-  if (isb) tile -= g.a.ntiles;
-  const float *X = isb ? g.b.X : g.a.X;
-  const int64_t ld = isb ? g.b.ld : g.a.ld;
-  const int64_t n = isb ? g.b.n : g.a.n;
-  const int64_t col_base = isb ? g.b.col_base : g.a.col_base;
-  const bool vec_ok = isb ? g.b.vec_ok : g.a.vec_ok;
-
-  const int64_t lbeg = (int64_t)s * g.rows_per_split;
-  const int64_t lend = min(g.rows, lbeg + g.rows_per_split);
-  if (lbeg >= lend) return;
-
+  SkWork w;
+  if (!sk_decode(g, w)) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int q = lane & 15, ph = lane >> 4;
-  const int64_t tile_col = (int64_t)tile * (16 * W * NV);
+  const int64_t tile_col = (int64_t)w.tile * (16 * W * NV);
   const int64_t col = tile_col + wave * (16 * NV) + q * NV;
-  const int mt0 = kc * MT;            // first m-tile of this workgroup
-  const int c0 = mt0 * 16;
+  const int c0 = w.kc * MT * 16;
 
   v4f acc[MT][NV];
 #pragma unroll
@@ -212,42 +138,13 @@ __global__ __launch_bounds__(64 * W) void sketch_kernel(SkArgs g) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) ksum[v] = kcmp[v] = 0.0f;
 
-  const bool full = vec_ok && tile_col + 16 * W * NV <= n;
-  if (full)
-    sketch_loop<MT, NV, W, KC, true>(g, X, ld, n, vec_ok, lbeg, lend, col, c0, P, P + PBUF, acc, ksum, kcmp);
-  else
-    sketch_loop<MT, NV, W, KC, false>(g, X, ld, n, vec_ok, lbeg, lend, col, c0, P, P + PBUF, acc, ksum, kcmp);
-
-  // ---- epilogue: partial sketches (FP32) and partial squared norms (FP64)
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double nrm = (double)ksum[v] - (double)kcmp[v];
-    nrm += __shfl_xor(nrm, 16, 64);
-    nrm += __shfl_xor(nrm, 32, 64);
-    const int64_t c_ = col + v;
-    if (c_ < n && ph == 0 && kc == 0) {
-      double *dst = g.npart + (int64_t)s * g.ntot + col_base + c_;
-      *dst += nrm;
-    }
+  if (w.lbeg < w.lend) {   // an empty split still stores its zero partials
+    if (w.vec_ok && tile_col + 16 * W * NV <= w.n)
+      sketch_loop<MT, NV, W, KC, true>(g, w, col, c0, P, P + PBUF, acc, ksum, kcmp);
+    else
+      sketch_loop<MT, NV, W, KC, false>(g, w, col, c0, P, P + PBUF, acc, ksum, kcmp);
   }
-#pragma unroll
-  for (int i = 0; i < MT; ++i) {
-    if (mt0 + i < g.mt_total) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int64_t c_ = col + v;
-        if (c_ < n) {
-          float *dst = g.part + ((int64_t)s * g.ntot + col_base + c_) * g.kpad + c0 + 16 * i + 4 * ph;
-          float4 old = *reinterpret_cast<float4 *>(dst);
-          old.x += acc[i][v][0];
-          old.y += acc[i][v][1];
-          old.z += acc[i][v][2];
-          old.w += acc[i][v][3];
-          *reinterpret_cast<float4 *>(dst) = old;
-        }
-      }
-    }
-  }
+  sk_epilogue<MT, NV>(g, w, col, c0, ph, acc, ksum, kcmp);
 }
 
 using KernelPtr = void (*)(SkArgs);
@@ -347,8 +244,9 @@ __global__ void pi_fill_kernel(int64_t l0, int64_t nrows, int k, uint64_t seed, 
 // re-read their data tile (from L2). SMP_SKETCH_TILE="nv,mt[,waves[,kc]]"
 // overrides the choice (for tuning sweeps); kc is the number of data rows per
 // streaming chunk.
-SketchPlan sketch_plan(int k) {
-  SketchPlan p;
+static SketchPlan sketch_plan_fp32(int k) {
+  SketchPlan p{};
+  p.prec = SMP_PREC_FP32;
   p.mt_total = (k + 15) / 16;
   int nv = 2, cap = 13, waves = 8, kc = 32;
   if (const char *e = getenv("SMP_SKETCH_TILE")) {
@@ -368,44 +266,96 @@ SketchPlan sketch_plan(int k) {
   p.mt = (p.mt_total + p.kt - 1) / p.kt;
   p.ncol_tile = 16 * waves * p.nv;
   p.kpad = p.mt_total * 16;
+  p.kernel = reinterpret_cast<void *>(kernel_for(nv, p.mt, waves, kc));
   return p;
 }
 
+SketchPlan sketch_plan(int k, int prec) {
+  return prec == SMP_PREC_BF16 ? sketch_plan_bf16(k) : sketch_plan_fp32(k);
+}
+
+int sketch_slots(const SketchPlan &pl) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    cus = 256;
+  if (!pl.kernel || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<KernelPtr>(pl.kernel),
+                                                                 64 * pl.waves, 0) != hipSuccess)
+    per_cu = 1;
+  hipGetLastError();
+  return std::max(1, cus) * std::max(1, per_cu);
+}
+
 hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
-                       int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, float *part,
-                       double *npart, hipStream_t st) {
-  if (rows <= 0) return hipSuccess;
-  KernelPtr kern = kernel_for(pl.nv, pl.mt, pl.waves, pl.kc);
-  if (!kern) return hipErrorInvalidValue;
+                       int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, bool accumulate,
+                       float *part, double *npart, hipStream_t st) {
+  if (rows < 0) return hipErrorInvalidValue;
   SkArgs g{};
   const int nct = pl.ncol_tile;
   const int vb = 4 * pl.nv;   // bytes of one lane's vector load
-  g.a = SkMat{A, lda, n1, 0, (int)((n1 + nct - 1) / nct),
-              (int)(lda % pl.nv == 0 && ((uintptr_t)A % (vb > 16 ? 16 : vb)) == 0)};
+  // vector loads need an aligned base, a leading dimension and a column count
+  // that are multiples of nv
+  auto vec_ok = [&](const float *X, int64_t ld, int64_t n) {
+    return ld % pl.nv == 0 && n % pl.nv == 0 && ((uintptr_t)X % (vb > 16 ? 16 : vb)) == 0;
+  };
+  g.a = SkMat{A, lda, n1, 0, (int)((n1 + nct - 1) / nct), (int)vec_ok(A, lda, n1)};
   if (B) {
-    g.b = SkMat{B, ldb, n2, n1, (int)((n2 + nct - 1) / nct),
-                (int)(ldb % pl.nv == 0 && ((uintptr_t)B % (vb > 16 ? 16 : vb)) == 0)};
+    g.b = SkMat{B, ldb, n2, n1, (int)((n2 + nct - 1) / nct), (int)vec_ok(B, ldb, n2)};
   } else {
-    g.b = SkMat{nullptr, 0, 0, n1, 0, 0};
+    g.b = SkMat{nullptr, 0, 0, n1, 0, 1};
   }
-  g.row0 = row0;
-  g.rows = rows;
-  g.S = S;
-  int64_t rps = (rows + S - 1) / S;
-  rps = (rps + pl.kc - 1) / pl.kc * pl.kc;
-  g.rows_per_split = rps;
   g.ntot = n1 + n2;
   g.k = k;
   g.kpad = pl.kpad;
   g.kt = pl.kt;
   g.mt_total = pl.mt_total;
+  g.accumulate = accumulate ? 1 : 0;
   g.seed = seed;
   g.part = part;
   g.npart = npart;
-  const int64_t nlog = (int64_t)g.kt * (g.a.ntiles + g.b.ntiles) * S;
-  const int64_t grid = (nlog + 7) / 8 * 8;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * pl.waves), 0, st, g);
-  return hipGetLastError();
+  auto launch = [&](KernelPtr kern, int64_t r0, int64_t nrows, int splits, int64_t rps, int s_base) {
+    g.row0 = r0;
+    g.rows = nrows;
+    g.S = splits;
+    g.rows_per_split = rps;
+    g.s_base = s_base;
+    const int64_t nlog = (int64_t)g.kt * (g.a.ntiles + g.b.ntiles) * splits;
+    const int64_t grid = (nlog + 7) / 8 * 8;
+    const float *Xa = g.a.X, *Xb = g.b.X;
+    g.a.X = Xa + (r0 - row0) * lda;   // the kernels index rows from the launch's first row
+    if (Xb) g.b.X = Xb + (r0 - row0) * ldb;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * pl.waves), 0, st, g);
+    g.a.X = Xa;
+    g.b.X = Xb;
+    return hipGetLastError();
+  };
+
+  if (pl.prec != SMP_PREC_BF16) {
+    if (rows == 0) return hipSuccess;
+    KernelPtr kern = reinterpret_cast<KernelPtr>(pl.kernel);
+    if (!kern) return hipErrorInvalidValue;
+    int64_t rps = (rows + S - 1) / S;
+    rps = (rps + pl.kc - 1) / pl.kc * pl.kc;
+    return launch(kern, row0, rows, S, rps, 0);
+  }
+
+  // BF16: a main launch over S splits of whole Pi blocks, and a tail launch
+  // (one split, clamped) for the rows left over, into partial slot S. The
+  // tail launch also runs with no rows, so that a one-shot pass stores zeros
+  // in that slot.
+  const bool vec = g.a.vec_ok && g.b.vec_ok;
+  KernelPtr kmain = reinterpret_cast<KernelPtr>(vec ? pl.kernel : pl.kernel_scalar);
+  KernelPtr ktail = reinterpret_cast<KernelPtr>(vec ? pl.kernel_clamp : pl.kernel_scalar);
+  if (!kmain || !ktail) return hipErrorInvalidValue;
+  const int64_t rps = rows / S / pl.kc * pl.kc;
+  const int64_t main_rows = rps * S;
+  if (main_rows > 0 || !accumulate) {   // with no whole block the one-shot pass still stores zero partials
+    const hipError_t e = launch(kmain, row0, main_rows, S, rps, 0);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t tail = rows - main_rows;
+  if (tail == 0 && accumulate) return hipSuccess;
+  return launch(ktail, row0 + main_rows, tail, 1, (tail + pl.kc - 1) / pl.kc * pl.kc, S);
 }
 
 hipError_t sketch_finish(const SketchPlan &pl, const float *part, const double *npart, int S, int64_t n1,

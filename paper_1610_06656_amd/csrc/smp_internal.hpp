@@ -27,23 +27,39 @@ namespace smp {
 
 // ---- sketch --------------------------------------------------------------------
 struct SketchPlan {
+  int prec;       // smp_precision of the MFMA operands
   int mt_total;   // ceil(k/16) m-tiles of 16 sketch rows
   int kt;         // WG chunks along k
   int mt;         // m-tiles per chunk
   int nv;         // adjacent columns per lane: a wave covers 16*nv columns
-  int waves;      // waves per workgroup (4 or 8), sharing one Pi block
-  int kc;         // data rows per streaming chunk (16 or 32)
+  int waves;      // waves per workgroup, sharing one Pi block
+  int kc;         // data rows per Pi block (the streaming chunk)
   int ncol_tile;  // columns per WG = waves * 16 * nv
   int kpad;       // mt_total * 16
+  void *kernel;         // the instantiated kernel for this shape
+  void *kernel_clamp;   // BF16: variant for partial blocks (the tail launch), else null
+  void *kernel_scalar;  // BF16: variant with guarded scalar loads (unaligned or ragged inputs), else null
 };
 
-SketchPlan sketch_plan(int k);
+// Partial-sketch slots a pass with S splits writes: S, plus one for the rows
+// the BF16 main launch leaves to its tail launch.
+inline int sketch_slots_total(const SketchPlan &pl, int S) { return pl.prec == SMP_PREC_BF16 ? S + 1 : S; }
+
+// Tile plan for sketch size k and operand precision prec.
+SketchPlan sketch_plan(int k, int prec);
+SketchPlan sketch_plan_bf16(int k);
+
+// Workgroups of the plan's kernel that the device runs at once
+// (CUs x resident workgroups per CU).
+int sketch_slots(const SketchPlan &pl);
 
 // Pass over rows [row0, row0+rows) of A (and B). part: [S][n1+n2][kpad] FP32,
-// npart: [S][n1+n2] FP64; zeroed by the caller before the first push.
+// npart: [S][n1+n2] FP64. accumulate: add into the partials (zeroed by the
+// caller before the first push); otherwise store them (a single push covering
+// all rows).
 hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
-                       int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, float *part,
-                       double *npart, hipStream_t st);
+                       int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, bool accumulate,
+                       float *part, double *npart, hipStream_t st);
 
 // Reduce the S partials into At (n1 x k), Bt (n2 x k), na2, nb2 (Bt/nb2 may be null).
 hipError_t sketch_finish(const SketchPlan &pl, const float *part, const double *npart, int S, int64_t n1,

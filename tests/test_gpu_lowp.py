@@ -1,0 +1,223 @@
+"""GPU parity of the BF16 sketch variant (operands rounded to bfloat16, FP32
+accumulation) against the oracle's definition of it (``sketch_lowp``: the
+exact product of the rounded operands), and of the BF16 solve end to end.
+
+Tolerances (derived from the arithmetic):
+  sketch  per column ||dA~_i|| / ||A~_i|| <= 2e-4. The GPU rounds its FP32
+          Box-Muller draw (hardware log/sin/cos, a few FP32 ulps from the FP64
+          value) to bfloat16, the oracle its FP64 draw. The two roundings differ
+          where the draw lies within ~4 ulp_32 of a bfloat16 rounding midpoint:
+          probability ~2^-14 per entry, each such entry moving its product by
+          one bfloat16 ulp (2^-8 relative). Summed over d rows with random
+          signs this is sqrt(2^-14) * 2^-8 ~ 3e-5 of the column norm; FP32
+          accumulation adds ~1e-6.
+  norms   unrounded FP32 data, compensated sums: relative 1e-6 (as FP32).
+  solve   e_gpu within 1e-3 (relative) of the oracle's e with the same
+          BF16 definition of the sketch: the sketch differences above move
+          the estimates M~_ij by ~1e-4 relative at most.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import smp_inputs
+from conftest import gpu_available
+from gpu_common import DEV, SEED, latent, log
+from oracle import evaluate as oev
+from oracle import gaussian, philox, rounding
+from oracle import sketch as osk
+from oracle import solve as oso
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL_SKETCH = 2e-4
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1610_06656_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def _col_rel(got_t, ref):
+    g = got_t.T.astype(np.float64)
+    num = np.linalg.norm(g - ref, axis=0)
+    den = np.maximum(np.linalg.norm(ref, axis=0), 1e-300)
+    return float(np.max(num / den))
+
+
+def _bf16_params(api, d, n1, n2, k, **kw):
+    return api.make_params(d, n1, n2, k, r=1, prec=api.SMP_PREC_BF16, **kw)
+
+
+def _sketch_gpu(api, ctx, p, Ad, Bd, n1, n2, k):
+    At = torch.empty(n1, k, device=DEV)
+    Bt = torch.empty(n2, k, device=DEV)
+    na2 = torch.empty(n1, device=DEV)
+    nb2 = torch.empty(n2, device=DEV)
+    ctx.smp_sketch(p, Ad, Bd, At, Bt, na2, nb2)
+    torch.cuda.synchronize()
+    return At.cpu().numpy(), Bt.cpu().numpy(), na2.cpu().numpy(), nb2.cpu().numpy()
+
+
+SKETCH_CASES = {
+    "c1": dict(d=2000, n1=200, n2=200, k=50),
+    "ragged": dict(d=1037, n1=77, n2=131, k=37),
+    "k400_tiles": dict(d=20000, n1=300, n2=1100, k=400),
+    "k1024_chunks": dict(d=4096, n1=129, n2=64, k=1024),
+    "tiny": dict(d=3, n1=1, n2=5, k=1),
+    "one_block_tail": dict(d=130, n1=513, n2=2, k=81),
+}
+
+
+@pytest.mark.parametrize("name", list(SKETCH_CASES))
+def test_sketch_bf16_parity(api, ctx, name):
+    c = SKETCH_CASES[name]
+    log(f"bf16 sketch {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=min(5, c["n1"], c["n2"]))
+    p = _bf16_params(api, c["d"], c["n1"], c["n2"], c["k"])
+    At, Bt, na2, nb2 = _sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"])
+    oAt, oBt, ona2, onb2 = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, c["k"], "bf16")
+    ea, eb = _col_rel(At, oAt), _col_rel(Bt, oBt)
+    log(f"  column rel err A {ea:.2e} B {eb:.2e}")
+    assert ea < TOL_SKETCH and eb < TOL_SKETCH
+    assert np.allclose(na2, ona2, rtol=1e-6, atol=0)
+    assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
+
+
+def test_sketch_bf16_scalar_path_zero_column_and_b_is_a(api, ctx):
+    d, n1, n2, k = 700, 45, 33, 21
+    A, B, _, _ = latent(d, n1, n2)
+    A[:, 7] = 0.0
+    Afull = torch.zeros(d, n1 + 3)
+    Afull[:, :n1] = A
+    Ad = Afull.to(DEV)[:, :n1]                 # lda = n1 + 3 (odd): scalar load path
+    p = _bf16_params(api, d, n1, n2, k)
+    At, Bt, _, _ = _sketch_gpu(api, ctx, p, Ad, B.to(DEV), n1, n2, k)
+    oAt, oBt, _, _ = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, k, "bf16")
+    assert np.all(At[7] == 0.0)
+    keep = np.arange(n1) != 7
+    assert _col_rel(At[keep], oAt[:, keep]) < TOL_SKETCH
+    assert _col_rel(Bt, oBt) < TOL_SKETCH
+    # B = A (PCA case)
+    n = 96
+    A2, _, Ad2, _ = latent(1500, n, n, same=True)
+    p2 = _bf16_params(api, 1500, n, n, 40, b_is_a=True)
+    At2 = torch.empty(n, 40, device=DEV)
+    Bt2 = torch.empty(n, 40, device=DEV)
+    na = torch.empty(n, device=DEV)
+    nb = torch.empty(n, device=DEV)
+    ctx.smp_sketch(p2, Ad2, None, At2, Bt2, na, nb)
+    torch.cuda.synchronize()
+    oAt2, _, _, _ = osk.sketch_lowp(A2.numpy(), None, p2.seed, 40, "bf16")
+    assert _col_rel(At2.cpu().numpy(), oAt2) < TOL_SKETCH
+    assert torch.equal(At2, Bt2)
+
+
+def test_sketch_bf16_streaming_push_any_order(api, ctx):
+    d, n1, n2, k = 3000, 130, 70, 64
+    A, B, Ad, Bd = latent(d, n1, n2)
+    p = _bf16_params(api, d, n1, n2, k)
+    st = ctx.smp_sketch_begin(p)
+    for l0, l1 in [(2000, 3000), (0, 1), (1, 1999), (1999, 2000)]:
+        ctx.smp_sketch_push(st, Ad[l0:l1], Bd[l0:l1], l0)
+    At = torch.empty(n1, k, device=DEV)
+    Bt = torch.empty(n2, k, device=DEV)
+    na2 = torch.empty(n1, device=DEV)
+    nb2 = torch.empty(n2, device=DEV)
+    ctx.smp_sketch_end(st, At, Bt, na2, nb2)
+    torch.cuda.synchronize()
+    ctx.smp_sketch_free(st)
+    oAt, oBt, ona2, _ = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, k, "bf16")
+    assert _col_rel(At.cpu().numpy(), oAt) < TOL_SKETCH
+    assert _col_rel(Bt.cpu().numpy(), oBt) < TOL_SKETCH
+    assert np.allclose(na2.cpu().numpy(), ona2, rtol=1e-6)
+
+
+def _pi_rows_bf16(seed, k, rows_c, d):
+    """R(Z(c, l)) / sqrt(k) for selected sketch rows c and all l < d."""
+    out = np.empty((len(rows_c), d))
+    ls = np.arange(d, dtype=np.int64)
+    for t, c in enumerate(rows_c):
+        w = philox.stream_words(seed, philox.TAG_PI, ls, np.full(d, c // 4, dtype=np.int64))
+        out[t] = rounding.round_bf16(gaussian.normals_from_words(*w)[c % 4]) / np.sqrt(k)
+    return out
+
+
+def test_c2_bf16_sketch_sampled_outputs(api, ctx):
+    """d = 200,000, n1 = n2 = 2,000, k = 400 in the benchmark's launch
+    configuration: 16 sketch rows x 24 columns of A~ and B~ against the
+    oracle's BF16 definition computed one by one."""
+    c = smp_inputs.CONFIGS["c2_fp32"]
+    log("c2 bf16 sketch sampled")
+    Ad, Bd = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], SEED, device=DEV)
+    p = _bf16_params(api, c["d"], c["n1"], c["n2"], c["k"])
+    At, Bt, na2, _ = _sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"])
+    rng = np.random.default_rng(1)
+    rows_c = sorted(set(rng.choice(c["k"], 16, replace=False).tolist()) | {0, c["k"] - 1})
+    cols = sorted(set(rng.choice(c["n1"], 24, replace=False).tolist()) | {0, c["n1"] - 1})
+    P = _pi_rows_bf16(p.seed, c["k"], rows_c, c["d"])
+    for X, S in ((Ad, At), (Bd, Bt)):
+        Xs = rounding.round_bf16(X[:, cols].double().cpu().numpy())
+        ref = P @ Xs
+        got = S[cols][:, rows_c].astype(np.float64).T
+        col_rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        log(f"  max column rel {col_rel.max():.3e}")
+        assert col_rel.max() < TOL_SKETCH
+    ref_na2 = (Ad.double() ** 2).sum(0).cpu().numpy()
+    assert np.allclose(na2, ref_na2, rtol=1e-6)
+
+
+SOLVE_CASES = {
+    "c1": dict(d=2000, n1=200, n2=200, R=5, k=50, r=5, T=10),
+    "ragged": dict(d=1037, n1=77, n2=131, R=3, k=37, r=3, T=8),
+    "k400_r10": dict(d=20000, n1=300, n2=260, R=10, k=400, r=10, T=10),
+}
+
+
+@pytest.mark.parametrize("name", list(SOLVE_CASES))
+def test_solve_bf16_matches_oracle(api, ctx, name):
+    c = SOLVE_CASES[name]
+    log(f"bf16 solve {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=c["R"])
+    m = api.default_m(c["n1"], c["n2"], c["r"])
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], m=m, prec=api.SMP_PREC_BF16,
+                        init_iters=40)
+    U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=DEV)
+    V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=DEV)
+    s = torch.empty(c["r"], dtype=torch.float64, device=DEV)
+    ctx.smp_solve(p, Ad, Bd, U, V, s)
+    torch.cuda.synchronize()
+    ref = oso.smp_pca(A.numpy(), B.numpy(), c["r"], c["k"], p.m, c["T"], SEED, sketch_fmt="bf16")
+    AtB = oev.product(A.numpy(), B.numpy())
+    e_gpu = oev.relative_error(AtB, U.cpu().numpy(), s.cpu().numpy(), V.cpu().numpy())
+    e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
+    log(f"  e_gpu={e_gpu:.6e} e_oracle_bf16={e_ora:.6e}")
+    assert abs(e_gpu - e_ora) <= 1e-3 * e_ora
+
+
+def test_c2_bf16_solve_error_against_fp64_oracle(api, ctx):
+    """The benchmark workload with the BF16 sketch: the spectral error stays
+    within 1.02x of the FP64 oracle's (plain FP64 sketch)."""
+    c = smp_inputs.CONFIGS["c2_fp32"]
+    log("c2 bf16 end to end")
+    Ad, Bd = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], SEED, device=DEV)
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], prec=api.SMP_PREC_BF16)
+    U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=DEV)
+    V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=DEV)
+    s = torch.empty(c["r"], dtype=torch.float64, device=DEV)
+    ctx.smp_solve(p, Ad, Bd, U, V, s)
+    torch.cuda.synchronize()
+    A, B = Ad.cpu().numpy(), Bd.cpu().numpy()
+    ref = oso.smp_pca(A, B, c["r"], c["k"], p.m, c["T"], SEED)
+    AtB = oev.product(A, B)
+    e_gpu = oev.relative_error(AtB, U.cpu().numpy(), s.cpu().numpy(), V.cpu().numpy())
+    e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
+    log(f"  e_gpu_bf16={e_gpu:.6e} e_oracle_fp64={e_ora:.6e} ratio={e_gpu / e_ora:.4f}")
+    assert e_gpu <= 1.02 * e_ora
