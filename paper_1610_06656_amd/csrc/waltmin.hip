@@ -9,7 +9,7 @@
 //
 // Iterations (Alg. 2 steps 7-10): each half-step is one weighted least-squares
 // problem per output row, min_v sum_e w_e (q_e^T v - M~_e)^2 over the row's
-// sampled entries, with q the rows of the orthonormalised fixed factor. The
+// sampled entries, with q the rows of the fixed factor. The
 // normal equations G = sum w q q^T, h = sum w M~ q are accumulated on the FP64
 // matrix cores (v_mfma_f64_16x16x4f64: four sampled entries per instruction,
 // operand A = w q^T, operand B = [q | M~]), copied to LDS, and solved there by
@@ -20,9 +20,10 @@
 // Orthonormalisation is CholeskyQR (Fukaya et al. 2014): Gram X^T X (fixed
 // reduction order), LDS Cholesky, X <- X L^-T. A pivot below 1e-13 of the
 // largest diagonal entry drops that direction (its column becomes 0). The
-// fixed factor of a half-step and the inner subspace iterations take one pass
-// (only the span matters there); factors that must be orthonormal (the final
-// V, the last block of the init) take two (CholeskyQR2).
+// inner subspace iterations take one pass (only the span matters there);
+// factors that must be orthonormal (the final V, the last block of the init)
+// take two (CholeskyQR2). The fixed factor of a half-step is not
+// orthonormalised (see waltmin_run).
 // Small symmetric eigenproblems use a parallel cyclic Jacobi method
 // (round-robin ordering, one wave).
 //
@@ -714,10 +715,14 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   if (T == 0) {
     hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
   } else {
+    // Alg. 2 orthonormalises the fixed factor before each half-step. The
+    // least-squares solution for the other factor only changes basis with it
+    // (U -> U R gives V -> V R^-T), so U V^T is the same; the factors are
+    // orthonormalised once, before the last half-step, which also gives the
+    // orthonormal V that the canonical form needs.
     for (int t = 0; t < T; ++t) {
-      orth1(w, w.U, n1, r, st);                                         // Q_U
       ls_solve(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 2 * t + 1, w.U, r, n2, w.V, st);
-      if (t + 1 < T) orth1(w, w.V, n2, r, st); else orth(w, w.V, n2, r, st);   // Q_V
+      if (t + 1 == T) orth(w, w.V, n2, r, st);   // Q_V
       ls_solve(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 2 * t + 2, w.V, r, n1, w.U, st);
     }
   }
