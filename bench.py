@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the CPU-oracle sample (0: all d rows)")
+    ap.add_argument("--workload", choices=("c2", "batch", "serve"), default="c2",
+                    help="c2: the headline solve (default); batch: 512 jobs of the batching mix through the "
+                         "server; serve: Poisson arrivals of the serving mix")
+    ap.add_argument("--workers", type=int, default=4, help="server worker threads (batch, serve)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window of the serve workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 2^30 bytes (the reference dispatch for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -144,12 +149,116 @@ def leg_summary(leg):
             "spectral_error": leg["err"]}
 
 
+def _pools(spec, count, d, n, seed, dev):
+    import smp_inputs
+    return [smp_inputs.latent_pair(d, n, n, spec["R"], spec["sigma"], spec["alpha"], seed + 7919 * i, device=dev)
+            for i in range(count)]
+
+
+def run_mix(api, jobs, pools, large_pool, prec, workers, arrivals=None):
+    """Run the jobs through one server; arrivals (seconds from start) or all
+    at once. Returns timing and latency figures."""
+    import threading
+
+    import torch
+    dev = pools[0][0].device
+    work = []
+    for j in jobs:
+        A, B = large_pool if j["large"] else pools[j["pool"]]
+        d, n, r = j["d"], j["n"], j["r"]
+        p = api.make_params(d, n, n, j["k"], r, T=10, seed=j["seed"], prec=prec)
+        outs = (torch.empty(n, r, dtype=torch.float64, device=dev), torch.empty(n, r, dtype=torch.float64, device=dev),
+                torch.empty(r, dtype=torch.float64, device=dev))
+        work.append((p, A[:d, :n], B[:d, :n], outs, 8.0 * d * n, j["large"]))
+    torch.cuda.synchronize()
+    srv = api.Server(0, workers=workers)
+    ids = [None] * len(work)
+    results = [None] * len(work)
+
+    def waiter():
+        for i in range(len(work)):
+            while ids[i] is None:
+                time.sleep(0.0002)
+            results[i] = srv.wait(ids[i])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i, (p, A, B, outs, _, _) in enumerate(work):
+        if arrivals is not None:
+            delay = t0 + arrivals[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+        ids[i] = srv.submit(p, A, B, *outs)
+    th.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = [r["queue_ms"] + r["run_ms"] for r in results]
+    out = {"jobs": len(work), "failed": sum(r["status"] != 0 for r in results), "wall_s": round(wall, 4),
+           "solves_per_s": round(len(work) / wall, 2),
+           "input_gbps": round(sum(w[4] for w in work) / wall / 1e9, 2),
+           "latency_ms": {"p50": round(pct(lat, 50), 3), "p99": round(pct(lat, 99), 3)},
+           "run_ms": {"p50": round(pct([r["run_ms"] for r in results], 50), 3),
+                      "p99": round(pct([r["run_ms"] for r in results], 99), 3)},
+           "max_running": st["max_running"]}
+    big = [l for l, w in zip(lat, work) if w[5]]
+    if big:
+        small = [l for l, w in zip(lat, work) if not w[5]]
+        out["latency_ms_large"] = {"p50": round(pct(big, 50), 3), "p99": round(pct(big, 99), 3), "count": len(big)}
+        out["latency_ms_small"] = {"p50": round(pct(small, 50), 3), "p99": round(pct(small, 99), 3)}
+    return out
+
+
+def main_mix(args):
+    import torch
+
+    import smp_inputs
+    from paper_1610_06656_amd import api
+
+    dev = torch.device("cuda:0")
+    b, sv = smp_inputs.BATCH, smp_inputs.SERVE
+    seed = smp_inputs.SEED_BASE
+    pools = _pools(b, b["pools"], b["d"][1], b["n"][1], seed, dev)
+    if args.workload == "batch":
+        jobs = smp_inputs.job_mix(b["jobs"], seed)
+        large_pool, arrivals = None, None
+        desc = (f"{b['jobs']} independent jobs: d uniform in [10k, 200k], n1 = n2 uniform in [128, 2048], "
+                f"r in {{5, 10, 20}}, k = r * uniform{{4..20}}, T = 10, m = 4nr ln n; latent rank 10, noise 0.1, "
+                f"column scale (j+1)^-0.5; inputs are top-left blocks of {b['pools']} resident 200000 x 2048 pairs")
+    else:
+        L = sv["large"]
+        large_pool = _pools(sv, 1, L["d"], L["n"], seed + 1, dev)[0]
+        g = torch.Generator().manual_seed(seed)
+        arrivals, t = [], 0.0
+        while True:
+            t += float(torch.empty(1).exponential_(sv["rate_per_s"], generator=g))
+            if t > args.serve_seconds:
+                break
+            arrivals.append(t)
+        jobs = smp_inputs.job_mix(len(arrivals), seed, large_frac=sv["large_frac"])
+        desc = (f"Poisson arrivals at {sv['rate_per_s']:.0f} jobs/s for {args.serve_seconds:.1f} s: the batching mix "
+                f"plus {100 * sv['large_frac']:.0f}% large jobs (d = 1M, n1 = n2 = 4096, r = 20; latent rank 20, "
+                f"noise 0.05, column scale (j+1)^-0.7); inputs are blocks of resident pairs")
+    torch.cuda.synchronize()
+    legs = {}
+    for name, prec in (("bf16", api.SMP_PREC_BF16), ("fp32", api.SMP_PREC_FP32)):
+        run_mix(api, jobs[:8], pools, large_pool, prec, args.workers)          # warm-up (workspaces, code)
+        legs[name] = run_mix(api, jobs, pools, large_pool, prec, args.workers, arrivals)
+    out = {"metric": METRIC, "workload": args.workload, "value": legs["bf16"]["solves_per_s"], "unit": "solves/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": desc, "workers": args.workers}, "bf16": legs["bf16"], "fp32": legs["fp32"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
                                    "described in DESIGN.md but not built)"}))
         sys.exit(2)
+    if args.workload != "c2":
+        return main_mix(args)
     import torch
 
     import smp_inputs

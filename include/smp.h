@@ -178,8 +178,10 @@ smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, cons
  * Init: top-r left/right singular subspace of R = w .* P_Omega0(M~) by block
  * subspace iteration; rows of U0 with ||U0_i|| > 8 sqrt(r) sqrt(na2_i / F_A)
  * are zeroed (trim). T alternating steps: V_j = argmin sum_i w_ij (q_i^T v - M~_ij)^2
- * with q the orthonormalised U, then the same for U against the orthonormalised
- * V; every r x r system is solved by FP64 Cholesky (pivot <= 1e-12 max diag:
+ * with q the rows of U, then the same for U against V (Alg. 2 orthonormalises
+ * the fixed factor first; that changes only the basis of the solution, not
+ * U V^T, so it is done once, on V before the last step); every r x r system
+ * is solved by FP64 Cholesky (pivot <= 1e-12 max diag:
  * retry on G + 1e-9 tr(G)/r I; else 0). Output in canonical form
  * U V^T -> U diag(sigma) V^T with U (n1 x r), V (n2 x r) orthonormal and
  * sigma (r, descending; may be NULL, then sigma is folded into U). */
@@ -201,6 +203,56 @@ smp_status smp_stage_times(smp_ctx *ctx, float *ms, int n);
  * intermediates. Outputs as smp_waltmin. B may equal A (or SMP_B_IS_A). */
 smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
                      double *U, double *V, double *sigma);
+
+/* ---- batching and serving: many independent jobs on one GPU ------------------
+ * A server runs jobs (each one smp_solve) on `workers` threads, each with its
+ * own context, HIP stream and workspace, so the kernels of different jobs
+ * overlap on the device (continuous batching: a job submitted while others
+ * run starts as soon as a worker is free and the HBM budget allows). Jobs are
+ * admitted in submission order while the sum of the library workspace of the
+ * running jobs (smp_workspace_size) stays within `hbm_budget` bytes; a job
+ * larger than the budget runs when nothing else does. 0 means no budget.
+ * The caller owns every job's inputs and outputs (device memory of the
+ * server's device) and keeps them alive and untouched until the job is
+ * waited for. Results are the same as smp_solve of the job alone.
+ * smp_server_destroy runs the jobs still queued to completion first. */
+typedef struct smp_server smp_server;
+
+typedef struct smp_job_result {
+  int32_t status;    /* smp_status of the job's smp_solve */
+  int32_t worker;    /* index of the worker that ran it */
+  double queue_ms;   /* submission -> start */
+  double run_ms;     /* start -> completion (includes the final stream synchronisation) */
+} smp_job_result;
+
+typedef struct smp_server_stats {
+  int64_t submitted, completed, failed;
+  int32_t max_running;        /* most jobs running at once */
+  int32_t workers;
+  int64_t max_budget_in_use;  /* largest sum of admitted workspace (bytes) */
+} smp_server_stats;
+
+/* workers in [1, 16]. Creates the worker threads and their contexts. */
+smp_status smp_server_create(int device, int workers, size_t hbm_budget, smp_server **out);
+/* Validates p (as smp_check_params) and the pointers, queues the job and
+ * returns its id. Does not block on the GPU. */
+smp_status smp_server_submit(smp_server *s, const smp_params *p, const float *A, int64_t lda, const float *B,
+                             int64_t ldb, double *U, double *V, double *sigma, uint64_t *job_id);
+/* Blocks until the job has finished; fills *res (may be NULL) and forgets the
+ * job. SMP_ERR_INVALID_ARG for an unknown or already waited id. The job's
+ * own status is res->status; its error text, when it failed, is returned by
+ * smp_server_last_error until the next wait. */
+smp_status smp_server_wait(smp_server *s, uint64_t job_id, smp_job_result *res);
+const char *smp_server_last_error(const smp_server *s);
+smp_status smp_server_get_stats(smp_server *s, smp_server_stats *st);
+void smp_server_destroy(smp_server *s);
+
+/* Runs njobs jobs through a temporary server (workers, hbm_budget as above)
+ * and waits for all. Arrays have njobs entries; res may be NULL. Returns
+ * SMP_OK when every job succeeded, else the status of the first failed job. */
+smp_status smp_solve_batch(int device, int njobs, const smp_params *p, const float *const *A, const int64_t *lda,
+                           const float *const *B, const int64_t *ldb, double *const *U, double *const *V,
+                           double *const *sigma, int workers, size_t hbm_budget, smp_job_result *res);
 
 #ifdef __cplusplus
 }

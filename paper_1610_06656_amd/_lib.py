@@ -45,6 +45,17 @@ class SmpOmega(ctypes.Structure):
     ]
 
 
+class SmpJobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("worker", ctypes.c_int32),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double)]
+
+
+class SmpServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("max_running", ctypes.c_int32), ("workers", ctypes.c_int32),
+                ("max_budget_in_use", ctypes.c_int64)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "smp_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
@@ -76,6 +87,21 @@ EXPORTS = {
     "smp_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p]),
+    "smp_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "smp_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "smp_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(SmpJobResult)]),
+    "smp_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "smp_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpServerStats)]),
+    "smp_server_destroy": (None, [ctypes.c_void_p]),
+    "smp_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(SmpParams),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_size_t,
+                                       ctypes.POINTER(SmpJobResult)]),
 }
 
 _lib = None

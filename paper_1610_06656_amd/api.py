@@ -9,7 +9,7 @@ import math
 import torch
 
 from . import _lib
-from ._lib import SmpOmega, SmpParams
+from ._lib import SmpJobResult, SmpOmega, SmpParams, SmpServerStats
 from ._lib import SMP_B_IS_A, SMP_OMEGA_REUSE, SMP_OMEGA_SPLIT, SMP_PREC_BF16, SMP_PREC_FP32  # noqa: F401
 
 
@@ -207,6 +207,101 @@ class Context:
         self._check(self.lib.smp_solve(self.h, ctypes.byref(p), _ptr(A, torch.float32, "A", dense=False), A.stride(0),
                                        _ptr(Bp, torch.float32, "B", dense=False), Bp.stride(0), _ptr(U, torch.float64, "U"),
                                        _ptr(V, torch.float64, "V"), _ptr(sigma, torch.float64, "sigma")))
+
+
+def _job_dict(r):
+    return {"status": int(r.status), "worker": int(r.worker), "queue_ms": float(r.queue_ms),
+            "run_ms": float(r.run_ms)}
+
+
+class Server:
+    """smp_server: independent jobs (one smp_solve each) run by `workers`
+    threads, each with its own context and HIP stream, admitted in order
+    within `hbm_budget` bytes of library workspace (0: no budget). The
+    tensors of a job are kept referenced until the job is waited for."""
+
+    def __init__(self, device=0, workers=4, hbm_budget=0):
+        self.lib = _lib.load()
+        dev = torch.device(device if not isinstance(device, int) else f"cuda:{device}")
+        self.device = dev
+        h = ctypes.c_void_p()
+        st = self.lib.smp_server_create(dev.index or 0, int(workers), int(hbm_budget), ctypes.byref(h))
+        if st != 0:
+            raise SmpError(st, "smp_server_create failed")
+        self.h = h
+        self._held = {}
+
+    def submit(self, p, A, B, U, V, sigma=None):
+        """Queue one job; returns its id. The inputs must be complete on the
+        device: the current torch stream is synchronised first, because the
+        workers' streams do not wait on it."""
+        if A.stride(1) != 1 or (B is not None and B.stride(1) != 1):
+            raise ValueError("A and B must have unit column stride")
+        Bp = B if B is not None else A
+        torch.cuda.current_stream(self.device).synchronize()
+        jid = ctypes.c_uint64()
+        st = self.lib.smp_server_submit(self.h, ctypes.byref(p), _ptr(A, torch.float32, "A", dense=False), A.stride(0),
+                                        _ptr(Bp, torch.float32, "B", dense=False), Bp.stride(0),
+                                        _ptr(U, torch.float64, "U"), _ptr(V, torch.float64, "V"),
+                                        _ptr(sigma, torch.float64, "sigma"), ctypes.byref(jid))
+        if st != 0:
+            raise SmpError(st, "smp_server_submit rejected the job")
+        self._held[jid.value] = (p, A, B, U, V, sigma)
+        return jid.value
+
+    def wait(self, job_id):
+        """Block until the job is done; returns {status, worker, queue_ms,
+        run_ms} (and `error` when the job failed)."""
+        r = SmpJobResult()
+        st = self.lib.smp_server_wait(self.h, ctypes.c_uint64(job_id), ctypes.byref(r))
+        if st != 0:
+            raise SmpError(st, f"unknown job {job_id}")
+        self._held.pop(job_id, None)
+        out = _job_dict(r)
+        if r.status != 0:
+            out["error"] = self.lib.smp_server_last_error(self.h).decode()
+        return out
+
+    def stats(self):
+        s = SmpServerStats()
+        st = self.lib.smp_server_get_stats(self.h, ctypes.byref(s))
+        if st != 0:
+            raise SmpError(st, "smp_server_get_stats failed")
+        return {f: int(getattr(s, f)) for f, _ in SmpServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            self.lib.smp_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(jobs, device=0, workers=4, hbm_budget=0):
+    """smp_solve_batch over a list of jobs, each a dict with keys p, A, B
+    (None for A = B), U, V, sigma (optional). Returns the per-job results and
+    the batch status."""
+    lib = _lib.load()
+    n = len(jobs)
+    P = (SmpParams * n)(*[j["p"] for j in jobs])
+    vp = ctypes.c_void_p
+    A = (vp * n)(*[_ptr(j["A"], torch.float32, "A", dense=False) for j in jobs])
+    lda = (ctypes.c_int64 * n)(*[j["A"].stride(0) for j in jobs])
+    Bs = [j["B"] if j["B"] is not None else j["A"] for j in jobs]
+    B = (vp * n)(*[_ptr(b, torch.float32, "B", dense=False) for b in Bs])
+    ldb = (ctypes.c_int64 * n)(*[b.stride(0) for b in Bs])
+    U = (vp * n)(*[_ptr(j["U"], torch.float64, "U") for j in jobs])
+    V = (vp * n)(*[_ptr(j["V"], torch.float64, "V") for j in jobs])
+    S = (vp * n)(*[_ptr(j.get("sigma"), torch.float64, "sigma") for j in jobs])
+    res = (SmpJobResult * n)()
+    torch.cuda.current_stream().synchronize()
+    st = lib.smp_solve_batch(int(device), n, P, A, lda, B, ldb, U, V, S, int(workers), int(hbm_budget), res)
+    return st, [_job_dict(r) for r in res]
 
 
 def solve(A, B, k, r, T=10, m=None, seed=161006656, prec=_lib.SMP_PREC_FP32, omega_mode=_lib.SMP_OMEGA_REUSE,

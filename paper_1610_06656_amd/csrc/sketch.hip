@@ -172,15 +172,16 @@ ShapeTable *shape_tables(int &count) {
   static ShapeTable tabs[] = {
       {2, 4, 16, 25, {}}, {4, 4, 16, 12, {}}, {2, 8, 16, 13, {}}, {4, 8, 16, 7, {}}, {2, 8, 32, 13, {}},
   };
-  static bool init = false;
-  if (!init) {
+  // function-local statics initialise once, also under concurrent first calls
+  static const bool init = [] {
     KTable<2, 4, 16, 25>::fill(tabs[0].t);
     KTable<4, 4, 16, 12>::fill(tabs[1].t);
     KTable<2, 8, 16, 13>::fill(tabs[2].t);
     KTable<4, 8, 16, 7>::fill(tabs[3].t);
     KTable<2, 8, 32, 13>::fill(tabs[4].t);
-    init = true;
-  }
+    return true;
+  }();
+  (void)init;
   count = (int)(sizeof(tabs) / sizeof(tabs[0]));
   return tabs;
 }

@@ -340,12 +340,13 @@ Shape *shapes(int &count) {
   // the largest mt of each shape is the largest whose main kernel stays in
   // registers (no scratch) at two waves per SIMD
   static Shape tabs[] = {{4, 8, 4, 4, {}, {}, {}}, {2, 8, 4, 12, {}, {}, {}}};
-  static bool init = false;
-  if (!init) {
+  // function-local statics initialise once, also under concurrent first calls
+  static const bool init = [] {
     KTab<4, 8, 4, 4>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts);
     KTab<2, 8, 4, 12>::fill(tabs[1].t, tabs[1].tc, tabs[1].ts);
-    init = true;
-  }
+    return true;
+  }();
+  (void)init;
   count = (int)(sizeof(tabs) / sizeof(tabs[0]));
   return tabs;
 }

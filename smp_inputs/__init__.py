@@ -88,3 +88,35 @@ CONFIGS = {
     "c2_fp32": dict(d=200_000, n1=2000, n2=2000, R=10, sigma=0.1, alpha=0.5, k=400, r=10, T=10),
     "c3_precision": dict(d=1_000_000, n1=4096, n2=4096, R=20, sigma=0.05, alpha=0.7, k=1024, r=20, T=10),
 }
+
+# Job mixes for batching and serving: shapes and method parameters drawn per
+# job (no arithmetic of the method). Each job reads the top-left d x n block
+# of one of `pools` resident input pairs (generated at the largest shape with
+# their own seeds), and has its own seed for Pi and the sampling coins.
+BATCH = dict(jobs=512, d=(10_000, 200_000), n=(128, 2048), r=(5, 10, 20), k_over_r=(4, 20), R=10, sigma=0.1,
+             alpha=0.5, T=10, pools=8)
+SERVE = dict(rate_per_s=200.0, large_frac=0.05, large=dict(d=1_000_000, n=4096, r=20), R=20, sigma=0.05, alpha=0.7)
+
+
+def job_mix(count, seed, large_frac=0.0):
+    """`count` jobs as dicts (d, n, r, k, seed, pool, large) drawn as the
+    batching mix: d uniform in [10k, 200k], n uniform in [128, 2048],
+    r in {5, 10, 20}, k = r * uniform{4..20}; with probability large_frac a
+    job is large (d = 1M, n = 4096, r = 20)."""
+    rng = torch.Generator().manual_seed(int(seed))
+    b = BATCH
+    out = []
+    for i in range(count):
+        u = torch.rand(6, generator=rng).tolist()
+        large = u[5] < large_frac
+        if large:
+            L = SERVE["large"]
+            d, n, r = L["d"], L["n"], L["r"]
+        else:
+            d = int(b["d"][0] + u[0] * (b["d"][1] - b["d"][0]))
+            n = int(b["n"][0] + u[1] * (b["n"][1] - b["n"][0]))
+            r = b["r"][min(2, int(u[2] * 3))]
+        k = r * int(b["k_over_r"][0] + u[3] * (b["k_over_r"][1] - b["k_over_r"][0] + 1))
+        out.append(dict(d=d, n=n, r=r, k=min(k, 4096), seed=int(seed) * 1000003 + i,
+                        pool=int(u[4] * b["pools"]) % b["pools"], large=large))
+    return out

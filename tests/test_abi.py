@@ -38,6 +38,23 @@ def test_struct_layouts_match_header():
     # smp_params: 3 int64, 6 int32, double, uint64, 2 int32 -> 72 bytes
     assert ctypes.sizeof(_lib.SmpParams) == 72
     assert ctypes.sizeof(_lib.SmpOmega) == 4 * 8 + 10 * 8
+    assert ctypes.sizeof(_lib.SmpJobResult) == 2 * 4 + 2 * 8
+    assert ctypes.sizeof(_lib.SmpServerStats) == 3 * 8 + 2 * 4 + 8
+
+
+@pytest.mark.skipif(gpu_available(), reason="checks the behaviour without a GPU")
+def test_server_entry_points_without_gpu(lib):
+    h = ctypes.c_void_p()
+    assert lib.smp_server_create(0, 4, 0, ctypes.byref(h)) == _lib.SMP_ERR_INVALID_ARG   # no device
+    assert lib.smp_server_create(0, 0, 0, ctypes.byref(h)) == _lib.SMP_ERR_INVALID_ARG   # workers < 1
+    jid = ctypes.c_uint64()
+    p = _params()
+    assert lib.smp_server_submit(None, ctypes.byref(p), None, 0, None, 0, None, None, None,
+                                 ctypes.byref(jid)) == _lib.SMP_ERR_INVALID_ARG
+    assert lib.smp_server_wait(None, 1, None) == _lib.SMP_ERR_INVALID_ARG
+    lib.smp_server_destroy(None)
+    # an empty batch needs no device
+    assert lib.smp_solve_batch(0, 0, None, None, None, None, None, None, None, None, 4, 0, None) == _lib.SMP_OK
 
 
 def _params(**kw):
