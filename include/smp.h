@@ -87,7 +87,7 @@ typedef struct smp_params {
   uint32_t flags;     /* SMP_B_IS_A */
   double m;           /* sample-count parameter of Eq. (1); > 0 */
   uint64_t seed;      /* Philox key */
-  int32_t init_iters; /* subspace iterations of the WAltMin init; 0 = default (6) */
+  int32_t init_iters; /* subspace iterations of the WAltMin init; 0 = default (4) */
   int32_t reserved;   /* must be 0 */
 } smp_params;
 
@@ -239,9 +239,10 @@ smp_status smp_server_create(int device, int workers, size_t hbm_budget, smp_ser
 smp_status smp_server_submit(smp_server *s, const smp_params *p, const float *A, int64_t lda, const float *B,
                              int64_t ldb, double *U, double *V, double *sigma, uint64_t *job_id);
 /* Blocks until the job has finished; fills *res (may be NULL) and forgets the
- * job. SMP_ERR_INVALID_ARG for an unknown or already waited id. The job's
- * own status is res->status; its error text, when it failed, is returned by
- * smp_server_last_error until the next wait. */
+ * job. SMP_ERR_INVALID_ARG for an unknown or already waited id. Each id is
+ * waited for once, by one thread (different ids may be waited for from
+ * different threads). The job's own status is res->status; its error text,
+ * when it failed, is returned by smp_server_last_error until the next wait. */
 smp_status smp_server_wait(smp_server *s, uint64_t job_id, smp_job_result *res);
 const char *smp_server_last_error(const smp_server *s);
 smp_status smp_server_get_stats(smp_server *s, smp_server_stats *st);

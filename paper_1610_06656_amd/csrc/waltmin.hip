@@ -490,6 +490,10 @@ __global__ __launch_bounds__(256) void ls_solve_kernel(const int64_t *__restrict
   for (int e = t; e < D * D; e += 256) Gw[e] = ((Gw[e] + Gw[D * D + e]) + Gw[2 * D * D + e]) + Gw[3 * D * D + e];
   __syncthreads();
   const double *G = Gw;
+  // The r x r solve is serial in r: one wave runs it, ordering its LDS
+  // accesses with wavefront-scope fences instead of workgroup barriers.
+  if (wave != 0) return;
+  auto wsync = [] { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); };
 
   double mx = 0.0, tr = 0.0;
   for (int a = 0; a < r; ++a) {
@@ -500,49 +504,49 @@ __global__ __launch_bounds__(256) void ls_solve_kernel(const int64_t *__restrict
   for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
     const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
     const double tol = 1e-12 * (mx + shift);
-    for (int e = t; e < r * r; e += 256) {
+    for (int e = t; e < r * r; e += 64) {
       const int i = e / r, c = e % r;
       L[i * 32 + c] = G[i * D + c] + ((i == c) ? shift : 0.0);
     }
     if (t < r) hv[t] = G[t * D + r];
-    __syncthreads();
+    wsync();
     bool ok = true;
     for (int j = 0; j < r; ++j) {
       const double piv = L[j * 32 + j];
       if (!(piv > tol)) { ok = false; break; }
       const double d = sqrt(piv);
-      __syncthreads();
+      wsync();
       if (t == 0) L[j * 32 + j] = d;
-      for (int i = j + 1 + t; i < r; i += 256) L[i * 32 + j] /= d;
-      __syncthreads();
+      for (int i = j + 1 + t; i < r; i += 64) L[i * 32 + j] /= d;
+      wsync();
       const int m = r - j - 1;
-      for (int e = t; e < m * m; e += 256) {
+      for (int e = t; e < m * m; e += 64) {
         const int i = j + 1 + e / m, c = j + 1 + e % m;
         if (c <= i) L[i * 32 + c] -= L[i * 32 + j] * L[c * 32 + j];
       }
-      __syncthreads();
+      wsync();
     }
     if (!ok) {
-      __syncthreads();
+      wsync();
       continue;
     }
     // forward: L y = h (column-oriented, updates in index order)
     for (int i = 0; i < r; ++i) {
-      __syncthreads();
+      wsync();
       const double yi = hv[i] / L[i * 32 + i];
-      __syncthreads();
+      wsync();
       if (t == 0) hv[i] = yi;
-      for (int k = i + 1 + t; k < r; k += 256) hv[k] -= L[k * 32 + i] * yi;
+      for (int k = i + 1 + t; k < r; k += 64) hv[k] -= L[k * 32 + i] * yi;
     }
     // backward: L^T x = y
     for (int i = r - 1; i >= 0; --i) {
-      __syncthreads();
+      wsync();
       const double xi = hv[i] / L[i * 32 + i];
-      __syncthreads();
+      wsync();
       if (t == 0) hv[i] = xi;
-      for (int k = t; k < i; k += 256) hv[k] -= L[i * 32 + k] * xi;
+      for (int k = t; k < i; k += 64) hv[k] -= L[i * 32 + k] * xi;
     }
-    __syncthreads();
+    wsync();
     solved = true;
   }
   if (t < r) Xout[o * r + t] = solved ? hv[t] : 0.0;
@@ -684,7 +688,7 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   const int64_t n1 = om.n1, n2 = om.n2;
   const int r = prm.r, T = prm.T;
   const int p = std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample)));
-  const int iters = prm.init_iters > 0 ? prm.init_iters : 6;
+  const int iters = prm.init_iters > 0 ? prm.init_iters : 4;
   const bool split = prm.omega_mode == SMP_OMEGA_SPLIT;
   Ws w = carve_ws(wsbase, n1, n2, p, r);
   const uint8_t *scsr = split ? om.sub_csr : nullptr;

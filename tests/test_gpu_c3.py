@@ -1,0 +1,237 @@
+"""Parity at the full large-precision size: d = 1,000,000, n1 = n2 = 4,096,
+k = 1,024, r = 20 (latent rank 20, noise 0.05, column scale (j+1)^-0.7), FP32
+and BF16 sketch, and the PCA case A = B at the same size. The oracle cannot
+run this size end to end, so every stage is checked where the oracle can
+compute it: sketch entries one by one, the squared norms, Omega bit-exact from
+the GPU's norms, estimates on sampled entries, WAltMin from the GPU's Omega
+and estimates; the end-to-end spectral errors are compared across the two
+precisions and against the best rank-r error.
+
+Tolerances: as in test_gpu_stages / test_gpu_lowp, except the FP32 sketch:
+each split accumulates about 10^5 products in FP32, so its per-column
+relative error grows like 2^-24 sqrt(10^5) ~ 2e-5 (measured 1.4e-5); the gate
+is 5e-5.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import smp_inputs
+from conftest import gpu_available
+from gpu_common import DEV, SEED, fixed_FA, log, omega_to_host, product
+from oracle import estimate as oes
+from oracle import gaussian, philox, rounding
+from oracle import sample as osa
+from oracle import waltmin as owm
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+C3 = smp_inputs.CONFIGS["c3_precision"]
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1610_06656_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+@pytest.fixture(scope="module")
+def data():
+    log("c3 data")
+    A, B = smp_inputs.latent_pair(C3["d"], C3["n1"], C3["n2"], C3["R"], C3["sigma"], C3["alpha"], SEED, device=DEV)
+    torch.cuda.synchronize()
+    yield A, B
+    del A, B
+    torch.cuda.empty_cache()
+
+
+def _norms64(X, chunk=1 << 17):
+    out = torch.zeros(X.shape[1], dtype=torch.float64, device=X.device)
+    for l0 in range(0, X.shape[0], chunk):
+        x = X[l0:l0 + chunk].double()
+        out += (x * x).sum(0)
+    return out.cpu().numpy()
+
+
+def _sketch(api, ctx, X, Y, prec, same=False):
+    n1, n2, k = X.shape[1], (X if same else Y).shape[1], C3["k"]
+    p = api.make_params(C3["d"], n1, n2, k, C3["r"], prec=prec, b_is_a=same)
+    At = torch.empty(n1, k, device=DEV)
+    Bt = torch.empty(n2, k, device=DEV)
+    na2 = torch.empty(n1, device=DEV)
+    nb2 = torch.empty(n2, device=DEV)
+    ctx.smp_sketch(p, X, None if same else Y, At, Bt, na2, nb2)
+    torch.cuda.synchronize()
+    return p, At, Bt, na2, nb2
+
+
+def _pi_rows(seed, k, rows_c, d, bf16):
+    out = np.empty((len(rows_c), d))
+    ls = np.arange(d, dtype=np.int64)
+    for t, c in enumerate(rows_c):
+        w = philox.stream_words(seed, philox.TAG_PI, ls, np.full(d, c // 4, dtype=np.int64))
+        z = gaussian.normals_from_words(*w)[c % 4]
+        out[t] = (rounding.round_bf16(z) if bf16 else z) / np.sqrt(k)
+    return out
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_c3_sketch_sampled_outputs_and_norms(api, ctx, data, prec_name):
+    A, B = data
+    bf16 = prec_name == "bf16"
+    prec = api.SMP_PREC_BF16 if bf16 else api.SMP_PREC_FP32
+    log(f"c3 sketch {prec_name}")
+    p, At, Bt, na2, nb2 = _sketch(api, ctx, A, B, prec)
+    rng = np.random.default_rng(3)
+    rows_c = sorted(set(rng.choice(C3["k"], 6, replace=False).tolist()) | {0, C3["k"] - 1})
+    cols = sorted(set(rng.choice(C3["n1"], 10, replace=False).tolist()) | {0, C3["n1"] - 1})
+    P = _pi_rows(p.seed, C3["k"], rows_c, C3["d"], bf16)
+    tol = 2e-4 if bf16 else 5e-5
+    for X, S in ((A, At), (B, Bt)):
+        Xs = X[:, cols].double().cpu().numpy()
+        if bf16:
+            Xs = rounding.round_bf16(Xs)
+        ref = P @ Xs
+        got = S[cols][:, rows_c].double().cpu().numpy().T
+        col_rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        log(f"  max column rel {col_rel.max():.3e}")
+        assert col_rel.max() < tol
+    assert np.allclose(na2.cpu().numpy(), _norms64(A), rtol=1e-6, atol=0)
+    assert np.allclose(nb2.cpu().numpy(), _norms64(B), rtol=1e-6, atol=0)
+
+
+@pytest.fixture(scope="module")
+def bf16_stages(api, ctx, data):
+    """The BF16 pass, Omega and estimates at full size, kept for the
+    downstream checks."""
+    A, B = data
+    p, At, Bt, na2, nb2 = _sketch(api, ctx, A, B, api.SMP_PREC_BF16)
+    from paper_1610_06656_amd.api import Omega
+    n1, n2 = C3["n1"], C3["n2"]
+    cap = int(p.m + 6 * np.sqrt(p.m) + 64)
+    om = Omega(n1, n2, cap, DEV)
+    nnz = ctx.smp_sample(p, na2, nb2, om)
+    ctx.smp_estimate(p, At, Bt, na2, nb2, om)
+    torch.cuda.synchronize()
+    return dict(p=p, At=At, Bt=Bt, na2=na2, nb2=nb2, om=om, nnz=nnz)
+
+
+def test_c3_sample_bit_exact(api, bf16_stages):
+    s = bf16_stages
+    na = s["na2"].cpu().numpy().astype(np.float64)
+    nb = s["nb2"].cpu().numpy().astype(np.float64)
+    ref = osa.sample(na, nb, s["p"].m, s["p"].seed)
+    log(f"  |Omega| = {s['nnz']} (m = {s['p'].m:.0f})")
+    assert s["nnz"] == ref.nnz
+    h = omega_to_host(s["om"])
+    assert np.array_equal(h["rows"], ref.rows) and np.array_equal(h["cols"], ref.cols)
+    assert np.array_equal(h["w"].view(np.uint64), ref.w.view(np.uint64))
+
+
+def test_c3_estimates_on_sampled_entries(api, bf16_stages):
+    s = bf16_stages
+    h = omega_to_host(s["om"])
+    rng = np.random.default_rng(5)
+    pick = rng.choice(s["nnz"], 20000, replace=False)
+    At = s["At"].double().cpu().numpy().T
+    Bt = s["Bt"].double().cpu().numpy().T
+    na = s["na2"].cpu().numpy().astype(np.float64)
+    nb = s["nb2"].cpu().numpy().astype(np.float64)
+    rows, cols = h["rows"][pick], h["cols"][pick]
+    ref = oes.estimate(At, Bt, na, nb, rows, cols)
+    scale = np.sqrt(na[rows] * nb[cols])
+    assert np.max(np.abs(h["mt"][pick] - ref) / scale) < 1e-10
+
+
+def test_c3_waltmin_from_gpu_omega(api, ctx, bf16_stages):
+    s = bf16_stages
+    n1, n2, r, T = C3["n1"], C3["n2"], C3["r"], C3["T"]
+    h = omega_to_host(s["om"])
+    na32 = s["na2"].cpu().numpy()
+    ref = owm.waltmin(n1, n2, h["rows"], h["cols"], h["w"], h["mt"], r, T, na32.astype(np.float64), fixed_FA(na32))
+    X_ref = ref["U"] @ ref["V"].T
+    p = s["p"]
+    p.init_iters = 40
+    U = torch.empty(n1, r, dtype=torch.float64, device=DEV)
+    V = torch.empty(n2, r, dtype=torch.float64, device=DEV)
+    sg = torch.empty(r, dtype=torch.float64, device=DEV)
+    ctx.smp_waltmin(p, s["om"], s["na2"], U, V, sg)
+    torch.cuda.synchronize()
+    X = product(U.cpu().numpy(), sg.cpu().numpy(), V.cpu().numpy())
+    rel = np.linalg.norm(X - X_ref) / np.linalg.norm(X_ref)
+    log(f"  waltmin rel diff {rel:.3e}")
+    assert rel < 1e-6
+
+
+def _spectral_error(M, U, s, V, iters=80):
+    E = M - (U * s[None, :]) @ V.T
+
+    def norm2(X):
+        g = torch.Generator(device=X.device).manual_seed(11)
+        v = torch.randn(X.shape[1], dtype=torch.float64, device=X.device, generator=g)
+        for _ in range(iters):
+            v = X.T @ (X @ v)
+            v /= torch.linalg.vector_norm(v)
+        return torch.linalg.vector_norm(X @ v).item()
+
+    return norm2(E) / norm2(M)
+
+
+def test_c3_end_to_end_bf16_vs_fp32(api, ctx, data):
+    """Full solves at this size: the BF16 error within 1.02x of the FP32 one.
+    A^T B has rank about r here (latent rank 20, small noise), so the best
+    rank-r error is ~0 and the error is the sketch's (JL) error; both must
+    still capture most of A^T B (error well below 1)."""
+    A, B = data
+    n1, n2, r = C3["n1"], C3["n2"], C3["r"]
+    M = torch.zeros(n1, n2, dtype=torch.float64, device=DEV)
+    for l0 in range(0, C3["d"], 1 << 17):
+        M += A[l0:l0 + (1 << 17)].double().T @ B[l0:l0 + (1 << 17)].double()
+    sv = torch.linalg.svdvals(M)
+    opt = (sv[r] / sv[0]).item()
+    errs = {}
+    for name, prec in (("fp32", api.SMP_PREC_FP32), ("bf16", api.SMP_PREC_BF16)):
+        p = api.make_params(C3["d"], n1, n2, C3["k"], r, T=C3["T"], prec=prec)
+        U = torch.empty(n1, r, dtype=torch.float64, device=DEV)
+        V = torch.empty(n2, r, dtype=torch.float64, device=DEV)
+        s = torch.empty(r, dtype=torch.float64, device=DEV)
+        ctx.smp_solve(p, A, B, U, V, s)
+        torch.cuda.synchronize()
+        errs[name] = _spectral_error(M, U, s, V)
+    log(f"  optimal {opt:.5f} fp32 {errs['fp32']:.5f} bf16 {errs['bf16']:.5f}")
+    assert errs["bf16"] <= 1.02 * errs["fp32"]
+    assert max(errs.values()) < 0.5
+
+
+def test_c3_a_equals_b(api, ctx, data):
+    """The PCA case A^T A at the same size (BF16): sketch entries, Omega
+    bit-exact, and the diagonal estimates equal ||A_i||^2."""
+    A, _ = data
+    p, At, Bt, na2, nb2 = _sketch(api, ctx, A, None, api.SMP_PREC_BF16, same=True)
+    assert torch.equal(At, Bt) and torch.equal(na2, nb2)
+    rows_c = [0, 517, C3["k"] - 1]
+    cols = [0, 2048, C3["n1"] - 1]
+    P = _pi_rows(p.seed, C3["k"], rows_c, C3["d"], True)
+    ref = P @ rounding.round_bf16(A[:, cols].double().cpu().numpy())
+    got = At[cols][:, rows_c].double().cpu().numpy().T
+    assert np.max(np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)) < 2e-4
+    from paper_1610_06656_amd.api import Omega
+    cap = int(p.m + 6 * np.sqrt(p.m) + 64)
+    om = Omega(C3["n1"], C3["n1"], cap, DEV)
+    nnz = ctx.smp_sample(p, na2, na2, om)
+    ctx.smp_estimate(p, At, At, na2, na2, om)
+    torch.cuda.synchronize()
+    na = na2.cpu().numpy().astype(np.float64)
+    ref_om = osa.sample(na, na, p.m, p.seed)
+    assert nnz == ref_om.nnz
+    h = omega_to_host(om)
+    assert np.array_equal(h["rows"], ref_om.rows) and np.array_equal(h["cols"], ref_om.cols)
+    diag = h["rows"] == h["cols"]
+    assert diag.sum() > 0
+    assert np.allclose(h["mt"][diag], na[h["rows"][diag]], rtol=1e-12)
