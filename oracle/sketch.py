@@ -90,11 +90,18 @@ def sketch_lowp(A, B, seed, k, fmt, chunk=8192):
     At = (1/sqrt(k)) R(Z) R(A), Bt = (1/sqrt(k)) R(Z) R(B) with R the rounding
     of every entry to `fmt` (``oracle.rounding``) and the product exact (FP64
     here). The squared column norms are those of the unrounded data.
-    fmt: "bf16". Same return convention as ``sketch``."""
-    from .rounding import round_bf16
-    if fmt != "bf16":
+    fmt: "bf16" (both operands rounded to bfloat16) or "fp8" (Pi rounded to
+    E4M3; the data to E4M3 with one E8M0 scale per column and block of 32
+    global rows, see ``oracle.rounding.quantize_e4m3_blocks``; chunk is then
+    a multiple of 32). Same return convention as ``sketch``."""
+    from .rounding import quantize_e4m3_blocks, round_bf16, round_e4m3
+    if fmt == "bf16":
+        rnd_pi, rnd_x = round_bf16, lambda a, l0: round_bf16(a)
+    elif fmt == "fp8":
+        chunk = max(32, chunk // 32 * 32)
+        rnd_pi, rnd_x = round_e4m3, quantize_e4m3_blocks
+    else:
         raise ValueError(f"unknown format {fmt!r}")
-    rnd = round_bf16
     A = np.asarray(A)
     d, n1 = A.shape
     same = B is None
@@ -108,13 +115,13 @@ def sketch_lowp(A, B, seed, k, fmt, chunk=8192):
     nb2 = None if same else np.zeros(n2)
     for l0 in range(0, d, chunk):
         l1 = min(d, l0 + chunk)
-        Z = rnd(gaussian_block(seed, k, l0, l1))
+        Z = rnd_pi(gaussian_block(seed, k, l0, l1))
         a = np.asarray(A[l0:l1], dtype=np.float64)
-        At += Z @ rnd(a)
+        At += Z @ rnd_x(a, l0)
         na2 += np.einsum("li,li->i", a, a)
         if not same:
             b = np.asarray(B[l0:l1], dtype=np.float64)
-            Bt += Z @ rnd(b)
+            Bt += Z @ rnd_x(b, l0)
             nb2 += np.einsum("li,li->i", b, b)
     At /= np.sqrt(float(k))
     if same:

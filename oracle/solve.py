@@ -22,7 +22,7 @@ def default_m(n1, n2, r):
 
 def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None):
     """Run Alg. 1. A: d x n1, B: d x n2 or None (A = B, Section 3 Remark 3).
-    sketch_fmt: None for the FP64 pass, or a narrow format ("bf16") whose
+    sketch_fmt: None for the FP64 pass, or a narrow format ("bf16", "fp8") whose
     rounded operands form the sketches (``oracle.sketch.sketch_lowp``).
     Returns a dict with the output factors and every intermediate:
       At, Bt, na2, nb2      sketches and squared column norms (step 2)

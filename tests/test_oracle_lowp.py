@@ -85,3 +85,76 @@ def test_sketch_bf16_a_equals_b_shares_the_result():
     assert At is Bt and na2 is nb2
     At2, Bt2, _, _ = sketch.sketch_lowp(A, A, 2, 5, "bf16")
     assert np.array_equal(At, At2) and np.array_equal(At2, Bt2)
+
+
+# ---------------------------------------------------------------- FP8 E4M3 with E8M0 block scales
+
+def test_round_e4m3_matches_torch_in_range():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(200000) * np.exp2(rng.uniform(-14, 9, 200000))
+    x = x.astype(np.float32).astype(np.float64)
+    x = np.concatenate([x[np.abs(x) <= 448], [0.0, -0.0, 448.0, -448.0, 2.0 ** -9, 2.0 ** -6, 2.0 ** -7 * 1.0625]])
+    ours = rounding.round_e4m3(x)
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_round_e4m3_ties_and_subnormals():
+    cases = {
+        1.0 + 1 / 16: 1.0,          # tie between 1 (even) and 1.125 (odd)
+        1.0 + 3 / 16: 1.25,         # tie between 1.125 (odd) and 1.25 (even)
+        2.0 ** -9: 2.0 ** -9,       # smallest subnormal
+        2.0 ** -10: 0.0,            # half of it: tie to even (zero)
+        3 * 2.0 ** -10: 2.0 ** -8,  # 1.5 subnormal steps: tie to the even step 2
+        240.0: 240.0,
+        232.0: 224.0,               # tie between 224 (even) and 240 (odd)
+        -5.3: -5.5,                 # spacing 0.5 in [4, 8)
+    }
+    x = np.array(list(cases.keys()))
+    assert np.array_equal(rounding.round_e4m3(x), np.array(list(cases.values())))
+
+
+def test_mx_scale_exponent_is_the_smallest_fitting_power_of_two():
+    rng = np.random.default_rng(2)
+    amax = np.abs(rng.standard_normal(50000)) * np.exp2(rng.uniform(-60, 60, 50000))
+    amax = np.concatenate([amax.astype(np.float32).astype(np.float64), 448.0 * np.exp2(np.arange(-20, 21))])
+    e = rounding.mx_scale_exponent(amax)
+    assert np.all(amax <= 448.0 * np.exp2(e.astype(np.float64)))
+    assert np.all(amax > 448.0 * np.exp2(e.astype(np.float64) - 1))
+    assert np.array_equal(rounding.mx_scale_exponent(448.0 * np.exp2(np.arange(-20, 21))), np.arange(-20, 21))
+    assert rounding.mx_scale_exponent(np.array([0.0]))[0] == 0
+    assert rounding.mx_scale_exponent(np.array([1e-300]))[0] == -127      # clamped to the E8M0 range
+
+
+def test_e4m3_blocks_fit_the_range_and_the_rounding_bound():
+    rng = np.random.default_rng(3)
+    X = (rng.standard_normal((200, 9)) * np.exp2(rng.uniform(-20, 20, 9))).astype(np.float32).astype(np.float64)
+    Q = rounding.quantize_e4m3_blocks(X)
+    u = 2.0 ** -4
+    for b0 in range(0, 200, 32):
+        blk, q = X[b0:b0 + 32], Q[b0:b0 + 32]
+        sc = np.exp2(rounding.mx_scale_exponent(np.abs(blk).max(axis=0)).astype(np.float64))
+        assert np.all(np.abs(blk / sc) <= 448.0)
+        assert np.all(np.abs(q - blk) <= u * np.abs(blk) + 2.0 ** -10 * sc)
+        assert np.array_equal(q / sc, rounding.round_e4m3(q / sc))        # representable after scaling
+
+
+def test_sketch_fp8_within_the_rounding_bound_and_independent_of_chunking():
+    d, n, k, seed = 400, 6, 10, 13
+    rng = np.random.default_rng(4)
+    A = (rng.standard_normal((d, n)) * (np.arange(1, n + 1) ** -0.7)).astype(np.float32).astype(np.float64)
+    At, _, na2, _ = sketch.sketch_lowp(A, None, seed, k, "fp8", chunk=64)
+    At2, _, _, _ = sketch.sketch_lowp(A, None, seed, k, "fp8", chunk=96)
+    assert np.allclose(At, At2, rtol=0, atol=1e-13 * np.abs(At).max())      # blocks follow global rows
+    Ae, _, na2e, _ = sketch.sketch(A, None, seed, k)
+    assert np.allclose(na2, na2e, rtol=1e-14)
+    Z = np.abs(sketch.gaussian_block(seed, k, 0, d))
+    u = 2.0 ** -4
+    sc = np.empty_like(A)
+    for b0 in range(0, d, 32):
+        e = rounding.mx_scale_exponent(np.abs(A[b0:b0 + 32]).max(axis=0))
+        sc[b0:b0 + 32] = np.exp2(e.astype(np.float64))
+    bound = ((2 * u + u * u) * (Z @ np.abs(A)) + (1 + u) * (Z @ (2.0 ** -10 * sc))) / np.sqrt(k)
+    assert np.all(np.abs(At - Ae) <= bound * (1 + 1e-12))
+    rel = np.linalg.norm(At - Ae) / np.linalg.norm(Ae)
+    assert 1e-3 < rel < 0.2
