@@ -8,8 +8,9 @@ d = 200,000, n1 = n2 = 2,000, k = 400, r = 10, T = 10, m = 4 n r ln n
 (latent rank 10, noise 0.1, column scaling (j+1)^-0.5), with A and B already
 resident in HBM. `value` is input bytes consumed per second, 4 d (n1+n2) / t,
 of the BF16-sketch solve (sketch GEMM operands rounded to bfloat16, FP32
-accumulation, FP64 WAltMin); the same solve with the FP32 sketch is timed
-beside it ("fp32"), and each leg's spectral error is reported.
+accumulation, FP64 WAltMin); the same solve with the FP32 sketch ("fp32") and
+with the FP8 E4M3 block-scaled sketch ("fp8") is timed beside it, and each
+leg's spectral error is reported.
 
 Also reported: the dominant kernel's roofline (the sketch pass, timed with HIP
 events on the library's stream), per-stage times, solves/s with p50/p99
@@ -274,6 +275,7 @@ def main():
 
     fp32 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_FP32, args.steps, args.warmup)
     bf16 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_BF16, args.steps, args.warmup)
+    fp8 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_FP8, args.steps, args.warmup)
 
     in_bytes = bf16["in_bytes"]
     ms_step = bf16["ms_step"]
@@ -317,6 +319,7 @@ def main():
             "traffic": recorded_traffic("sketch_fp32_c2_traffic"),
             "kernel": "sketch_kernel (v_mfma_f32_16x16x4f32)", "kernel_ms": round(sk_fp32, 4),
             "flops_per_launch": flops}),
+        "fp8": leg_summary(fp8),
         "bf16_vs_fp32_solves": round(fp32["ms_step"] / bf16["ms_step"], 3),
     }
     if args.copy_calibration:

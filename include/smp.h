@@ -65,8 +65,14 @@ typedef enum smp_status {
 
 typedef enum smp_precision {
   SMP_PREC_FP32 = 0,        /* sketch GEMM operands FP32 (v_mfma_f32_16x16x4_f32) */
-  SMP_PREC_BF16 = 1         /* Pi and data rounded to bfloat16 (nearest even), FP32 accumulate
+  SMP_PREC_BF16 = 1,        /* Pi and data rounded to bfloat16 (nearest even), FP32 accumulate
                                (v_mfma_f32_16x16x32_bf16); the norms use the unrounded data */
+  SMP_PREC_FP8 = 2          /* Pi rounded to FP8 E4M3; data to E4M3 with one power-of-two (E8M0)
+                               scale per column and block of 32 rows (the smallest with
+                               max|x| <= 448 * scale); FP32 accumulate on the block-scaled
+                               v_mfma_scale_f32_16x16x128_f8f6f4; norms from the unrounded data.
+                               Streaming pushes must start on a multiple of 32 rows and hold a
+                               multiple of 32 rows unless they end at row d. */
 } smp_precision;
 
 typedef enum smp_omega_mode {

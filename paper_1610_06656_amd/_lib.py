@@ -20,6 +20,7 @@ SMP_ERR_STATE = 6
 
 SMP_PREC_FP32 = 0
 SMP_PREC_BF16 = 1
+SMP_PREC_FP8 = 2
 SMP_OMEGA_REUSE = 0
 SMP_OMEGA_SPLIT = 1
 SMP_B_IS_A = 1

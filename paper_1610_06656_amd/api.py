@@ -10,7 +10,7 @@ import torch
 
 from . import _lib
 from ._lib import SmpJobResult, SmpOmega, SmpParams, SmpServerStats
-from ._lib import SMP_B_IS_A, SMP_OMEGA_REUSE, SMP_OMEGA_SPLIT, SMP_PREC_BF16, SMP_PREC_FP32  # noqa: F401
+from ._lib import SMP_B_IS_A, SMP_OMEGA_REUSE, SMP_OMEGA_SPLIT, SMP_PREC_BF16, SMP_PREC_FP32, SMP_PREC_FP8  # noqa: F401
 
 
 class SmpError(RuntimeError):

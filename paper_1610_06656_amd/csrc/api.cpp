@@ -51,7 +51,7 @@ std::string check(const smp_params *p) {
   if (p->T < 0 || p->T > 1000) return "T must be in [0, 1000]";
   if (p->T > 127 && p->omega_mode == SMP_OMEGA_SPLIT) return "SPLIT mode needs 2T+1 <= 255 subsets";
   if (!(p->m > 0.0) || !std::isfinite(p->m)) return "m must be a finite positive number";
-  if (p->prec != SMP_PREC_FP32 && p->prec != SMP_PREC_BF16) return "unknown precision";
+  if (p->prec != SMP_PREC_FP32 && p->prec != SMP_PREC_BF16 && p->prec != SMP_PREC_FP8) return "unknown precision";
   if (p->omega_mode != SMP_OMEGA_REUSE && p->omega_mode != SMP_OMEGA_SPLIT) return "unknown omega_mode";
   if (p->init_iters < 0 || p->init_iters > 1000) return "init_iters must be in [0, 1000]";
   if (p->reserved != 0) return "reserved must be 0";
@@ -296,6 +296,8 @@ smp_status smp_sketch_push(smp_ctx *ctx, smp_sketch_state *st, const float *A_ro
   if (row0 < 0 || nrows < 0 || row0 + nrows > p.d) return fail(ctx, SMP_ERR_INVALID_ARG, "rows out of [0, d)");
   if (nrows == 0) return SMP_OK;
   if (!A_rows || lda < p.n1) return fail(ctx, SMP_ERR_INVALID_ARG, "A is NULL or lda < n1");
+  if (p.prec == SMP_PREC_FP8 && (row0 % 32 != 0 || (nrows % 32 != 0 && row0 + nrows != p.d)))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "FP8 pushes must cover whole 32-row scaling blocks");
   if (!same && (!B_rows || ldb < p.n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
   SMP_HIP(ctx, smp::sketch_push(st->plan, A_rows, lda, p.n1, same ? nullptr : B_rows, ldb, same ? 0 : p.n2, row0,
                                 nrows, p.k, p.seed, st->S, true, st->part, st->npart, ctx->stream));

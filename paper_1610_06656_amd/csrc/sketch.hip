@@ -272,7 +272,7 @@ static SketchPlan sketch_plan_fp32(int k) {
 }
 
 SketchPlan sketch_plan(int k, int prec) {
-  return prec == SMP_PREC_BF16 ? sketch_plan_bf16(k) : sketch_plan_fp32(k);
+  return prec == SMP_PREC_BF16 ? sketch_plan_bf16(k) : prec == SMP_PREC_FP8 ? sketch_plan_fp8(k) : sketch_plan_fp32(k);
 }
 
 int sketch_slots(const SketchPlan &pl) {
@@ -331,7 +331,7 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
     return hipGetLastError();
   };
 
-  if (pl.prec != SMP_PREC_BF16) {
+  if (pl.prec == SMP_PREC_FP32) {
     if (rows == 0) return hipSuccess;
     KernelPtr kern = reinterpret_cast<KernelPtr>(pl.kernel);
     if (!kern) return hipErrorInvalidValue;
@@ -340,7 +340,7 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
     return launch(kern, row0, rows, S, rps, 0);
   }
 
-  // BF16: a main launch over S splits of whole Pi blocks, and a tail launch
+  // BF16 / FP8: a main launch over S splits of whole Pi blocks, and a tail launch
   // (one split, clamped) for the rows left over, into partial slot S. The
   // tail launch also runs with no rows, so that a one-shot pass stores zeros
   // in that slot.

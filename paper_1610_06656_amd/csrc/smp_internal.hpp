@@ -37,17 +37,18 @@ struct SketchPlan {
   int ncol_tile;  // columns per WG = waves * 16 * nv
   int kpad;       // mt_total * 16
   void *kernel;         // the instantiated kernel for this shape
-  void *kernel_clamp;   // BF16: variant for partial blocks (the tail launch), else null
-  void *kernel_scalar;  // BF16: variant with guarded scalar loads (unaligned or ragged inputs), else null
+  void *kernel_clamp;   // BF16, FP8: variant for partial blocks (the tail launch), else null
+  void *kernel_scalar;  // BF16, FP8: variant with guarded scalar loads (unaligned or ragged inputs), else null
 };
 
 // Partial-sketch slots a pass with S splits writes: S, plus one for the rows
-// the BF16 main launch leaves to its tail launch.
-inline int sketch_slots_total(const SketchPlan &pl, int S) { return pl.prec == SMP_PREC_BF16 ? S + 1 : S; }
+// the BF16 / FP8 main launch leaves to its tail launch.
+inline int sketch_slots_total(const SketchPlan &pl, int S) { return pl.prec == SMP_PREC_FP32 ? S : S + 1; }
 
 // Tile plan for sketch size k and operand precision prec.
 SketchPlan sketch_plan(int k, int prec);
 SketchPlan sketch_plan_bf16(int k);
+SketchPlan sketch_plan_fp8(int k);
 
 // Workgroups of the plan's kernel that the device runs at once
 // (CUs x resident workgroups per CU).

@@ -1,6 +1,8 @@
-"""GPU parity of the BF16 sketch variant (operands rounded to bfloat16, FP32
-accumulation) against the oracle's definition of it (``sketch_lowp``: the
-exact product of the rounded operands), and of the BF16 solve end to end.
+"""GPU parity of the low-precision sketch variants against the oracle's
+definitions of them (``sketch_lowp``: the exact product of the rounded
+operands): BF16 (operands rounded to bfloat16, FP32 accumulation) and FP8
+(E4M3 operands with E8M0 data block scales, FP32 accumulation; tolerance with
+the FP8 tests below), and of the solves end to end.
 
 Tolerances (derived from the arithmetic):
   sketch  per column ||dA~_i|| / ||A~_i|| <= 2e-4. The GPU rounds its FP32
@@ -221,3 +223,81 @@ def test_c2_bf16_solve_error_against_fp64_oracle(api, ctx):
     e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
     log(f"  e_gpu_bf16={e_gpu:.6e} e_oracle_fp64={e_ora:.6e} ratio={e_gpu / e_ora:.4f}")
     assert e_gpu <= 1.02 * e_ora
+
+
+# ---------------------------------------------------------------- FP8 E4M3 with E8M0 block scales
+#
+# Tolerance: the GPU rounds its FP32 Box-Muller draw to E4M3, the oracle its
+# FP64 draw; they differ where the draw lies within a few FP32 ulps of an E4M3
+# rounding midpoint (probability ~2^-17 per entry), each such entry moving its
+# product by 2^-4 relative: sqrt(2^-17) * 2^-4 ~ 2e-4 of the column norm. The
+# data side is identical on both sides (same FP32 values, exact power-of-two
+# scaling, the same scale decisions). Gate 1e-3 per column.
+
+TOL_FP8 = 1e-3
+
+FP8_CASES = {
+    "c1": dict(d=2000, n1=200, n2=200, k=50),
+    "ragged": dict(d=1037, n1=77, n2=131, k=37),
+    "k400_tiles": dict(d=20000, n1=300, n2=1100, k=400),
+    "tiny": dict(d=3, n1=1, n2=5, k=1),
+    "block_tail": dict(d=333, n1=512, n2=6, k=81),
+}
+
+
+@pytest.mark.parametrize("name", list(FP8_CASES))
+def test_sketch_fp8_parity(api, ctx, name):
+    c = FP8_CASES[name]
+    log(f"fp8 sketch {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=min(5, c["n1"], c["n2"]))
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], r=1, prec=api.SMP_PREC_FP8)
+    At, Bt, na2, nb2 = _sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"])
+    oAt, oBt, ona2, onb2 = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, c["k"], "fp8")
+    ea, eb = _col_rel(At, oAt), _col_rel(Bt, oBt)
+    log(f"  column rel err A {ea:.2e} B {eb:.2e}")
+    assert ea < TOL_FP8 and eb < TOL_FP8
+    assert np.allclose(na2, ona2, rtol=1e-6, atol=0)
+    assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
+
+
+def test_sketch_fp8_streaming_push_on_block_boundaries(api, ctx):
+    d, n1, n2, k = 3000, 130, 70, 64
+    A, B, Ad, Bd = latent(d, n1, n2)
+    p = api.make_params(d, n1, n2, k, r=1, prec=api.SMP_PREC_FP8)
+    st = ctx.smp_sketch_begin(p)
+    with pytest.raises(api.SmpError):
+        ctx.smp_sketch_push(st, Ad[0:40], Bd[0:40], 0)          # 40 rows: not whole 32-row blocks
+    for l0, l1 in [(2016, 3000), (0, 32), (32, 2016)]:
+        ctx.smp_sketch_push(st, Ad[l0:l1], Bd[l0:l1], l0)
+    At = torch.empty(n1, k, device=DEV)
+    Bt = torch.empty(n2, k, device=DEV)
+    na2 = torch.empty(n1, device=DEV)
+    nb2 = torch.empty(n2, device=DEV)
+    ctx.smp_sketch_end(st, At, Bt, na2, nb2)
+    torch.cuda.synchronize()
+    ctx.smp_sketch_free(st)
+    oAt, oBt, _, _ = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, k, "fp8")
+    assert _col_rel(At.cpu().numpy(), oAt) < TOL_FP8
+    assert _col_rel(Bt.cpu().numpy(), oBt) < TOL_FP8
+
+
+def test_solve_fp8_matches_oracle_and_reports_error(api, ctx):
+    c = dict(d=20000, n1=300, n2=260, R=10, k=400, r=10, T=10)
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=c["R"])
+    m = api.default_m(c["n1"], c["n2"], c["r"])
+    res = {}
+    for name, prec in (("fp8", api.SMP_PREC_FP8), ("fp32", api.SMP_PREC_FP32)):
+        p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], m=m, prec=prec, init_iters=40)
+        U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=DEV)
+        V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=DEV)
+        s = torch.empty(c["r"], dtype=torch.float64, device=DEV)
+        ctx.smp_solve(p, Ad, Bd, U, V, s)
+        torch.cuda.synchronize()
+        res[name] = (U.cpu().numpy(), s.cpu().numpy(), V.cpu().numpy(), p)
+    AtB = oev.product(A.numpy(), B.numpy())
+    ref8 = oso.smp_pca(A.numpy(), B.numpy(), c["r"], c["k"], res["fp8"][3].m, c["T"], SEED, sketch_fmt="fp8")
+    e8 = oev.relative_error(AtB, *res["fp8"][:3])
+    e32 = oev.relative_error(AtB, *res["fp32"][:3])
+    e8_ora = oev.relative_error(AtB, ref8["Uc"], ref8["sigma"], ref8["Vc"])
+    log(f"  e_fp8={e8:.6e} e_oracle_fp8={e8_ora:.6e} e_fp32={e32:.6e}")
+    assert abs(e8 - e8_ora) <= 5e-3 * e8_ora
