@@ -307,7 +307,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(hbm_gbps, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(hbm_gbps / PEAK_HBM_GBPS, 4),
                      "traffic": recorded_traffic("sketch_bf16_c2_traffic"),
-                     "kernel": "sketch_bf16_kernel (v_mfma_f32_16x16x32_bf16), main and tail launch",
+                     "kernel": "BF16 sketch pass: pi_store_bf16_kernel, then sketch_bf16_stored_kernel "
+                               "(v_mfma_f32_16x16x32_bf16) main and tail launch, timed together",
                      "kernel_ms": round(sk_bf16, 4), "bytes_per_launch": in_bytes},
         "solves_per_s": round(1e3 / ms_step, 3),
         "latency_ms": {"p50": round(pct(bf16["lat"], 50), 4), "p99": round(pct(bf16["lat"], 99), 4)},

@@ -133,6 +133,8 @@ struct smp_sketch_state {
   int S;
   float *part;
   double *npart;
+  void *pi = nullptr;    // stored-Pi scratch of the largest push so far
+  size_t pi_bytes = 0;
   bool ended;
 };
 
@@ -238,6 +240,7 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes) {
   size_t s = 0;
   const int slots = smp::sketch_slots_total(pl, S);
   s += al((size_t)slots * nt * pl.kpad * 4) + al((size_t)slots * nt * 8);   // sketch partials
+  s += al(smp::sketch_pi_bytes(pl, p->d));                                  // stored Pi of the one-shot pass
   s += al(nt * k * 4) + al(nt * 4);                                       // sketches + norms
   s += al(64) + al(nt * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);   // sampling
   const double nnz = std::min<double>((double)p->n1 * (double)p->n2, p->m + 6.0 * std::sqrt(p->m) + 64.0);
@@ -299,8 +302,21 @@ smp_status smp_sketch_push(smp_ctx *ctx, smp_sketch_state *st, const float *A_ro
   if (p.prec == SMP_PREC_FP8 && (row0 % 32 != 0 || (nrows % 32 != 0 && row0 + nrows != p.d)))
     return fail(ctx, SMP_ERR_INVALID_ARG, "FP8 pushes must cover whole 32-row scaling blocks");
   if (!same && (!B_rows || ldb < p.n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
+  const size_t need = smp::sketch_pi_bytes(st->plan, nrows);
+  if (need > st->pi_bytes) {   // grow the stored-Pi scratch (earlier pushes may still read the old one)
+    SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (st->pi) hipFree(st->pi);
+    st->pi = nullptr;
+    st->pi_bytes = 0;
+    if (hipMalloc(&st->pi, need) != hipSuccess) {
+      hipGetLastError();
+      st->pi = nullptr;
+      return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "stored-Pi scratch allocation failed");
+    }
+    st->pi_bytes = need;
+  }
   SMP_HIP(ctx, smp::sketch_push(st->plan, A_rows, lda, p.n1, same ? nullptr : B_rows, ldb, same ? 0 : p.n2, row0,
-                                nrows, p.k, p.seed, st->S, true, st->part, st->npart, ctx->stream));
+                                nrows, p.k, p.seed, st->S, true, st->part, st->npart, st->pi, ctx->stream));
   return SMP_OK;
 }
 
@@ -329,6 +345,7 @@ void smp_sketch_free(smp_sketch_state *st) {
   hipStreamSynchronize(st->ctx->stream);
   hipFree(st->part);
   hipFree(st->npart);
+  if (st->pi) hipFree(st->pi);
   delete st;
 }
 
@@ -348,15 +365,17 @@ smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t
   const int64_t nt = p->n1 + n2;
   const int slots = smp::sketch_slots_total(pl, S);
   const size_t pb = al((size_t)slots * nt * pl.kpad * 4), nb = al((size_t)slots * nt * 8);
+  const size_t pib = al(smp::sketch_pi_bytes(pl, p->d));
   smp_ctx_bufs &b = bufs(ctx);
-  smp_status s = ensure(ctx, b.sketch, pb + nb);
+  smp_status s = ensure(ctx, b.sketch, pb + nb + pib);
   if (s != SMP_OK) return s;
   float *part = static_cast<float *>(b.sketch.p);
   double *npart = reinterpret_cast<double *>(static_cast<char *>(b.sketch.p) + pb);
+  void *pi = pib ? static_cast<char *>(b.sketch.p) + pb + nb : nullptr;
   for (bool &r : ctx->recorded) r = false;
   mark(ctx, kStSketch, false);
   SMP_HIP(ctx, smp::sketch_push(pl, A, lda, p->n1, same ? nullptr : B, ldb, n2, 0, p->d, p->k, p->seed, S, false,
-                                part, npart, ctx->stream));
+                                part, npart, pi, ctx->stream));
   mark(ctx, kStSketch, true);
   mark(ctx, kStFinish, false);
   SMP_HIP(ctx, smp::sketch_finish(pl, part, npart, slots, p->n1, n2, p->k, At, same ? nullptr : Bt, na2,

@@ -289,8 +289,9 @@ int sketch_slots(const SketchPlan &pl) {
 
 hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
                        int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, bool accumulate,
-                       float *part, double *npart, hipStream_t st) {
+                       float *part, double *npart, void *pi_buf, hipStream_t st) {
   if (rows < 0) return hipErrorInvalidValue;
+  if (pl.pi_stored && rows > 0 && !pi_buf) return hipErrorInvalidValue;
   SkArgs g{};
   const int nct = pl.ncol_tile;
   const int vb = 4 * pl.nv;   // bytes of one lane's vector load
@@ -316,6 +317,9 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   g.npart = npart;
   auto launch = [&](KernelPtr kern, int64_t r0, int64_t nrows, int splits, int64_t rps, int s_base) {
     g.row0 = r0;
+    // stored Pi: the launch's first row r0 is a whole number of 32-row blocks past row0
+    g.pi = pl.pi_stored ? static_cast<const char *>(pi_buf) + (size_t)((r0 - row0) / 32) * pl.mt_total * 1024
+                        : nullptr;
     g.rows = nrows;
     g.S = splits;
     g.rows_per_split = rps;
@@ -344,6 +348,10 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   // (one split, clamped) for the rows left over, into partial slot S. The
   // tail launch also runs with no rows, so that a one-shot pass stores zeros
   // in that slot.
+  if (pl.pi_stored) {
+    const hipError_t e = pi_store(pl, seed, row0, rows, k, pi_buf, st);
+    if (e != hipSuccess) return e;
+  }
   const bool vec = g.a.vec_ok && g.b.vec_ok;
   KernelPtr kmain = reinterpret_cast<KernelPtr>(vec ? pl.kernel : pl.kernel_scalar);
   KernelPtr ktail = reinterpret_cast<KernelPtr>(vec ? pl.kernel_clamp : pl.kernel_scalar);

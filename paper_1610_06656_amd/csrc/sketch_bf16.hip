@@ -6,9 +6,29 @@
 // the Pi entries are the same N(0,1) draws as in the FP32 pass (same Philox
 // counters), each rounded to BF16, so the two passes differ only by rounding.
 //
-// Structure. Each workgroup (8 waves) owns a tile of 16*8*NV data columns, a
-// chunk of MT*16 sketch rows and one of S row splits, and regenerates the Pi
-// block it needs (Pi is never stored). Per block of KP = 128 data rows:
+// Two passes share this file.
+//
+// Stored-Pi pass (the default). Pi is drawn once per push (one Philox call per
+// four sketch rows of a data row) into a scratch buffer in the MFMA A-operand
+// order, and the pass is a split-K GEMM over it: each workgroup (8 waves, two
+// per SIMD) owns 16*8*NV = 256 columns, a chunk of up to 13 m-tiles and one of
+// S row splits. Per K step of 32 rows every lane loads its 8 rows x NV
+// columns and each wave copies its share of the chunk's 1 KiB Pi fragments
+// into an LDS buffer, D steps ahead of use; the wave then multiplies all
+// m-tiles of the chunk for its 16*NV columns. At d = 200,000, n1 = n2 = 2,000,
+// k = 400 (kt = 2 chunks) the per-CU vector L1 is what bounds it: about 100
+// misses in flight per CU at 600-800 cycles of L2 latency, i.e. about 19
+// bytes per clock per CU, for 2.8 bytes of L1 fill per byte of data (the data
+// read by both chunks, Pi read by each of the 16 column tiles). A wider tile
+// or a single chunk would cut that ratio, but the accumulators of 256
+// columns x 400 sketch rows fill the register file (400 of the 512 registers
+// per lane at one wave per SIMD), and the compiler then shuttles them between
+// AGPRs and VGPRs every step.
+//
+// Regenerating pass (SMP_SKETCH_BF16_STORED=0; needs no scratch). Each
+// workgroup (8 waves) owns a tile of 16*8*NV data columns, a chunk of MT*16
+// sketch rows and one of S row splits, and regenerates the Pi block it needs.
+// Per block of KP = 128 data rows:
 //  * Pi block: MT*16 sketch rows x KP data rows as BF16 in LDS, sketch-row
 //    major, so the 8 consecutive data rows one MFMA lane needs are one 16-byte
 //    read. Each thread makes MT Philox calls per block (4 sketch rows of one
@@ -40,6 +60,7 @@ namespace smp {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -124,7 +145,6 @@ __device__ __forceinline__ void convert_step(const Row<NV> (&x)[8], v8bf (&b)[NV
     uint32_t w[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) w[e] = pack_bf16(x[2 * e][v], x[2 * e + 1][v]);
-    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
     b[v] = __builtin_bit_cast(v8bf, (v4u){w[0], w[1], w[2], w[3]});
   }
 }
@@ -361,6 +381,246 @@ KernelPtr bf16_kernel_for(int nv, int mt, int waves, int gs, int variant) {
   return nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// Stored-Pi variant. Pi is drawn once per pass (one Philox call per four sketch
+// rows of a data row, as above) into a buffer laid out in the A-operand order
+// of v_mfma_f32_16x16x32_bf16, and the pass itself is a split-K GEMM that
+// streams that buffer through LDS. Every workgroup then covers all m-tiles of
+// its chunk for 16*8*NV columns, so a data tile crosses the CU's vector-memory
+// path once per chunk instead of once per 4-tile chunk, and no column tile
+// repeats the Philox work.
+//
+// Buffer layout: 16-byte unit (b * mt_total + i) * 64 + t holds, for lane
+// t = 16 g + q, the BF16 entries of sketch row 16 i + q at the data rows
+// 32 b + 8 g + (0..7) of the pass (b: 32-row block from the pass's first
+// row). One (b, i) pair is 1 KiB, the operand of one MFMA.
+
+constexpr int kPiUnit = 64;   // 16-byte units per (block, m-tile) fragment
+
+// Thread u of the grid fills lanes 16 g + 4 q4 + (0..3) of fragment u / 16
+// (g, q4 from u % 16): eight Philox calls (rows 32 b + 8 g + e, sketch rows
+// 16 i + 4 q4 .. +3) and four 16-byte stores that are contiguous across the
+// 16 threads of one fragment. Rows past nrows and sketch rows >= k are zero.
+__global__ __launch_bounds__(256) void pi_store_bf16_kernel(uint64_t seed, int64_t r0, int64_t nrows, int k,
+                                                            int mt_total, int64_t frags, v4u *__restrict__ out) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (u >= frags * 16) return;
+  const int64_t frag = u >> 4;
+  const int sub = (int)(u & 15);
+  const int g = sub >> 2, q4 = sub & 3;
+  const int i = (int)(frag % mt_total);
+  const int64_t blk = frag / mt_total;
+  const int c = 16 * i + 4 * q4;
+  float z[8][4];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t l = 32 * blk + 8 * g + e;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (l < nrows && c < k) v = normals4(stream_call(seed, kTagPi, (uint64_t)(r0 + l), (uint32_t)(c >> 2)));
+    z[e][0] = v.x;
+    z[e][1] = c + 1 < k ? v.y : 0.f;
+    z[e][2] = c + 2 < k ? v.z : 0.f;
+    z[e][3] = c + 3 < k ? v.w : 0.f;
+  }
+  v4u *dst = out + frag * kPiUnit + 16 * g + 4 * q4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    dst[j] = v4u{pack_bf16(z[0][j], z[1][j]), pack_bf16(z[2][j], z[3][j]), pack_bf16(z[4][j], z[5][j]),
+                 pack_bf16(z[6][j], z[7][j])};
+}
+
+// One K step of the stored-Pi pass: MT x NV MFMAs whose A fragments are read
+// from LDS in groups of G, the next group's reads issued before this group's
+// products so that the LDS latency overlaps the matrix cores.
+template <int MT, int NV, int G>
+__device__ __forceinline__ void mfma_step_stored(const v8bf (&b)[NV], const v4u *Lc, int lane, v4f (&acc)[MT][NV]) {
+  constexpr int NG = (MT + G - 1) / G;
+  v8bf a[2][G];
+#pragma unroll
+  for (int j = 0; j < G; ++j)
+    if (j < MT) a[0][j] = __builtin_bit_cast(v8bf, Lc[j * kPiUnit + lane]);
+#pragma unroll
+  for (int gr = 0; gr < NG; ++gr) {
+    if (gr + 1 < NG) {
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int i = (gr + 1) * G + j;
+        if (i < MT) a[(gr + 1) & 1][j] = __builtin_bit_cast(v8bf, Lc[i * kPiUnit + lane]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int i = gr * G + j;
+      if (i < MT) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          acc[i][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[gr & 1][j], b[v], acc[i][v], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Per K step t of 32 rows: issue the data loads and the Pi fragment loads of
+// step t + D into register set t % D (D steps of loads in flight, so that one
+// workgroup per CU covers the memory latency), multiply step t (Pi from LDS
+// buffer t % D), then store step t + 1's fragments into LDS buffer
+// (t + 1) % D and convert its rows. Wave w copies fragments w, w + W, ... of
+// the chunk (one 1 KiB fragment per load instruction). Fragments of m-tiles
+// past the chunk's valid ones are stored as zeros, so every wave runs the same
+// MT x NV products.
+//
+// The loop body has no data-dependent branches: the steps run in whole groups
+// of D, prefetches past the last step re-load the last step, and steps past
+// the end land zero Pi fragments and add nothing to the norms. (With the
+// issue and the landing under conditions, the compiler cannot prove that a
+// register set's previous loads have completed and waits for every load in
+// flight before reusing it, which serialises the prefetch.)
+template <int NV, bool NORM, bool CLAMP>
+__device__ __forceinline__ void finish_rows_if(const Row<NV> (&x)[8], int64_t row, int64_t row_last, bool valid,
+                                               v8bf (&b)[NV], float (&ksum)[NV], float (&kcmp)[NV]) {
+  if constexpr (NORM) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float s8 = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        s8 = (!CLAMP || row + e <= row_last) ? __builtin_fmaf(x[e][v], x[e][v], s8) : s8;
+      kahan_add(ksum[v], kcmp[v], valid ? s8 : 0.0f);
+    }
+  }
+  convert_step<NV>(x, b);
+}
+
+template <int MT, int NV, int G, int W, int D, bool VEC, bool CLAMP, bool NORM>
+__device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &w, int64_t col, int i0, int mv,
+                                                 v4u *L, v4f (&acc)[MT][NV], float (&ksum)[NV], float (&kcmp)[NV]) {
+  constexpr int CPW = (MT + W - 1) / W;
+  constexpr int LT = CPW * W;   // m-tile slots per LDS buffer
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, gq = lane >> 4;
+  const int64_t row_last = w.lend - 1;
+  const int64_t lcol = VEC ? (col < w.n - NV ? col : w.n - NV) : col;
+  const v4u *pi = reinterpret_cast<const v4u *>(g.pi) + (int64_t)i0 * kPiUnit + lane;
+  const int64_t fstride = (int64_t)g.mt_total * kPiUnit;   // units per 32-row block
+  const int64_t blk0 = w.lbeg / kStep;
+  const int64_t nsteps = (w.lend - w.lbeg + kStep - 1) / kStep;
+
+  RowAddr ra;
+  ra.base = w.X + w.lbeg * w.ld;
+  ra.ld = (uint32_t)w.ld;
+  ra.lane_off = (uint32_t)(8 * gq) * ra.ld + (uint32_t)lcol;
+  ra.nrows = w.lend - w.lbeg;
+  Row<NV> raw[D][8];
+  v4u pst[D][CPW];
+  v8bf b[NV];
+  auto issue = [&](int set, int64_t t) {   // t < nsteps; every load is unconditional (see above)
+    load_step<NV, VEC, CLAMP>(w, ra, kStep * t, gq, lcol, raw[set]);
+    const v4u *src = pi + (blk0 + t) * fstride;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int i = wave + W * j;
+      pst[set][j] = src[(i < mv ? i : mv - 1) * kPiUnit];
+    }
+  };
+  auto land = [&](int set, int64_t t) {   // step t's loads: Pi into LDS buffer `set`, rows into b
+    const bool valid = t < nsteps;
+    v4u *Ld = L + set * (LT * kPiUnit);
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int i = wave + W * j;   // tiles mv .. LT-1 get zeros (the padding m-tiles stay zero)
+      Ld[i * kPiUnit + lane] = (valid && i < mv) ? pst[set][j] : v4u{0u, 0u, 0u, 0u};
+    }
+    finish_rows_if<NV, NORM, CLAMP>(raw[set], w.lbeg + kStep * t + 8 * gq, row_last, valid, b, ksum, kcmp);
+  };
+
+#pragma unroll
+  for (int d = 0; d < D; ++d) issue(d, d < nsteps ? d : nsteps - 1);
+  land(0, 0);
+  for (int64_t t0 = 0; t0 < nsteps; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int64_t t = t0 + d;
+      __syncthreads();   // step t's fragments are in LDS; buffer (t + 1) % D is no longer read
+      issue(d, t + D < nsteps ? t + D : nsteps - 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_step_stored<MT, NV, G>(b, L + d * (LT * kPiUnit), lane, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      land((d + 1) % D, t + 1);
+    }
+  }
+}
+
+template <int MT, int NV, int G, int W, int D, bool VEC, bool CLAMP>
+__global__ __launch_bounds__(64 * W) void sketch_bf16_stored_kernel(SkArgs g) {
+  constexpr int LT = (MT + W - 1) / W * W;
+  __shared__ __attribute__((aligned(16))) v4u L[D * LT * kPiUnit];
+
+  SkWork w;
+  if (!sk_decode(g, w)) return;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int q = lane & 15, gq = lane >> 4;
+  const int64_t col = (int64_t)w.tile * (16 * W * NV) + wave * (16 * NV) + q * NV;
+  const int i0 = w.kc * MT;
+  const int mv = g.mt_total - i0 < MT ? g.mt_total - i0 : MT;
+
+  v4f acc[MT][NV];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[i][v] = v4f{0.f, 0.f, 0.f, 0.f};
+  float ksum[NV], kcmp[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ksum[v] = kcmp[v] = 0.0f;
+
+  if (w.lbeg < w.lend) {
+    if (w.kc == 0) loop_bf16_stored<MT, NV, G, W, D, VEC, CLAMP, true>(g, w, col, i0, mv, L, acc, ksum, kcmp);
+    else loop_bf16_stored<MT, NV, G, W, D, VEC, CLAMP, false>(g, w, col, i0, mv, L, acc, ksum, kcmp);
+  }
+  sk_epilogue<MT, NV>(g, w, col, i0 * 16, gq, acc, ksum, kcmp);
+}
+
+template <int NV, int G, int W, int D, int MT, int MT0>
+struct KTabS {
+  static void fill(KernelPtr *t, KernelPtr *tc, KernelPtr *ts) {
+    t[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, false>;
+    tc[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, true>;
+    ts[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, false, true>;
+    KTabS<NV, G, W, D, MT - 1, MT0>::fill(t, tc, ts);
+  }
+};
+template <int NV, int G, int W, int D, int MT0>
+struct KTabS<NV, G, W, D, MT0, MT0> {
+  static void fill(KernelPtr *, KernelPtr *, KernelPtr *) {}
+};
+
+struct ShapeS {
+  int nv, waves, depth, max_mt;
+  KernelPtr t[33], tc[33], ts[33];
+};
+
+ShapeS *shapes_stored(int &count) {
+  static ShapeS tabs[] = {{2, 8, 2, 13, {}, {}, {}}};
+  static const bool init = [] {
+    KTabS<2, 2, 8, 2, 13, 0>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts);
+    return true;
+  }();
+  (void)init;
+  count = (int)(sizeof(tabs) / sizeof(tabs[0]));
+  return tabs;
+}
+
+KernelPtr bf16_stored_kernel_for(int nv, int waves, int depth, int mt, int variant) {
+  int count = 0;
+  ShapeS *t = shapes_stored(count);
+  for (int i = 0; i < count; ++i)
+    if (t[i].nv == nv && t[i].waves == waves && t[i].depth == depth && mt >= 1 && mt <= t[i].max_mt && t[i].t[mt])
+      return variant == 0 ? t[i].t[mt] : variant == 1 ? t[i].tc[mt] : t[i].ts[mt];
+  return nullptr;
+}
+
 }  // namespace
 
 // Tile choice. Two per-CU resources bound the pass: the vector-memory path
@@ -372,7 +632,7 @@ KernelPtr bf16_kernel_for(int nv, int mt, int waves, int gs, int variant) {
 // (kt = 7) are the fastest; for larger k the 256-column tiles of up to 12
 // m-tiles keep kt lower. SMP_SKETCH_TILE_BF16="nv,mt[,waves[,gs]]" overrides
 // the choice (tuning sweeps).
-SketchPlan sketch_plan_bf16(int k) {
+static SketchPlan sketch_plan_bf16_regen(int k) {
   SketchPlan p{};
   p.prec = SMP_PREC_BF16;
   p.mt_total = (k + 15) / 16;
@@ -402,6 +662,55 @@ SketchPlan sketch_plan_bf16(int k) {
   p.kernel_clamp = reinterpret_cast<void *>(bf16_kernel_for(nv, p.mt, waves, gs, 1));
   p.kernel_scalar = reinterpret_cast<void *>(bf16_kernel_for(nv, p.mt, waves, gs, 2));
   return p;
+}
+
+// Stored-Pi plan: tiles of 16 * waves * nv columns, at most `cap` m-tiles per
+// workgroup, `depth` K steps of loads in flight.
+// SMP_SKETCH_BF16_STORED="nv,waves,depth,cap" picks the shape, "0" selects
+// the regenerating pass above.
+SketchPlan sketch_plan_bf16(int k) {
+  int nv = 2, waves = 8, depth = 2, cap = 13;
+  if (const char *e = getenv("SMP_SKETCH_BF16_STORED")) {
+    int env[4] = {0, 0, 0, 0};
+    const int got = sscanf(e, "%d,%d,%d,%d", &env[0], &env[1], &env[2], &env[3]);
+    if (got == 1 && env[0] == 0) return sketch_plan_bf16_regen(k);
+    if (got == 4 && bf16_stored_kernel_for(env[0], env[1], env[2], env[3], 0)) {
+      nv = env[0];
+      waves = env[1];
+      depth = env[2];
+      cap = env[3];
+    }
+  }
+  SketchPlan p{};
+  p.prec = SMP_PREC_BF16;
+  p.pi_stored = 1;
+  p.mt_total = (k + 15) / 16;
+  p.nv = nv;
+  p.waves = waves;
+  p.kc = kStep;
+  p.kt = (p.mt_total + cap - 1) / cap;
+  p.mt = (p.mt_total + p.kt - 1) / p.kt;
+  p.ncol_tile = 16 * waves * nv;
+  p.kpad = p.mt_total * 16;
+  p.kernel = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 0));
+  p.kernel_clamp = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 1));
+  p.kernel_scalar = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 2));
+  return p;
+}
+
+size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows) {
+  if (!pl.pi_stored || rows <= 0) return 0;
+  return (size_t)((rows + kStep - 1) / kStep) * (size_t)pl.mt_total * (kPiUnit * 16);
+}
+
+hipError_t pi_store(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
+                    hipStream_t st) {
+  if (!pl.pi_stored || rows <= 0) return hipSuccess;
+  const int64_t frags = (rows + kStep - 1) / kStep * pl.mt_total;
+  const int64_t grid = (frags * 16 + 255) / 256;
+  hipLaunchKernelGGL(pi_store_bf16_kernel, dim3((unsigned)grid), dim3(256), 0, st, seed, r0, rows, k, pl.mt_total,
+                     frags, static_cast<v4u *>(buf));
+  return hipGetLastError();
 }
 
 }  // namespace smp

@@ -1,4 +1,4 @@
-// Pieces shared by the FP32 and BF16 sketch kernels (Alg. 1 step 2): the
+// Pieces shared by the FP32, BF16 and FP8 sketch kernels (Alg. 1 step 2): the
 // launch arguments, the XCD-aware work decode, the data-row loads and the
 // split-K epilogue.
 #pragma once
@@ -24,6 +24,7 @@ struct SkArgs {
   int s_base;       // partial slot of split 0
   int accumulate;   // 1: add into the partials (streaming pushes); 0: store them (one-shot pass)
   uint64_t seed;
+  const void *pi;   // stored-Pi passes: the fragments of the launch's first 32-row block (else null)
   float *part;      // [S][ntot][kpad]
   double *npart;    // [S][ntot]
 };

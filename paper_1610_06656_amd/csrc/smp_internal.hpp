@@ -39,6 +39,7 @@ struct SketchPlan {
   void *kernel;         // the instantiated kernel for this shape
   void *kernel_clamp;   // BF16, FP8: variant for partial blocks (the tail launch), else null
   void *kernel_scalar;  // BF16, FP8: variant with guarded scalar loads (unaligned or ragged inputs), else null
+  int pi_stored;        // 1: Pi is drawn once per push into a buffer that the pass streams (BF16)
 };
 
 // Partial-sketch slots a pass with S splits writes: S, plus one for the rows
@@ -50,6 +51,11 @@ SketchPlan sketch_plan(int k, int prec);
 SketchPlan sketch_plan_bf16(int k);
 SketchPlan sketch_plan_fp8(int k);
 
+// Bytes of the stored-Pi buffer a push of `rows` rows needs (0 unless
+// pl.pi_stored), and the kernel that fills it for rows [r0, r0 + rows).
+size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows);
+hipError_t pi_store(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf, hipStream_t st);
+
 // Workgroups of the plan's kernel that the device runs at once
 // (CUs x resident workgroups per CU).
 int sketch_slots(const SketchPlan &pl);
@@ -57,10 +63,11 @@ int sketch_slots(const SketchPlan &pl);
 // Pass over rows [row0, row0+rows) of A (and B). part: [S][n1+n2][kpad] FP32,
 // npart: [S][n1+n2] FP64. accumulate: add into the partials (zeroed by the
 // caller before the first push); otherwise store them (a single push covering
-// all rows).
+// all rows). pi_buf: sketch_pi_bytes(pl, rows) bytes of scratch (may be null
+// when that is 0).
 hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
                        int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, bool accumulate,
-                       float *part, double *npart, hipStream_t st);
+                       float *part, double *npart, void *pi_buf, hipStream_t st);
 
 // Reduce the S partials into At (n1 x k), Bt (n2 x k), na2, nb2 (Bt/nb2 may be null).
 hipError_t sketch_finish(const SketchPlan &pl, const float *part, const double *npart, int S, int64_t n1,
