@@ -93,6 +93,23 @@ def test_sketch_bf16_parity(api, ctx, name):
     assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("name", ["c1", "ragged", "k1024_chunks", "one_block_tail"])
+def test_sketch_bf16_regenerating_pass_parity(api, ctx, name, monkeypatch):
+    """The BF16 pass that regenerates Pi inside each workgroup (selected with
+    SMP_SKETCH_BF16_STORED=0; the default pass stores Pi once per push) meets
+    the same bar against the oracle."""
+    monkeypatch.setenv("SMP_SKETCH_BF16_STORED", "0")
+    c = SKETCH_CASES[name]
+    log(f"bf16 regenerating sketch {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=min(5, c["n1"], c["n2"]))
+    p = _bf16_params(api, c["d"], c["n1"], c["n2"], c["k"])
+    At, Bt, na2, nb2 = _sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"])
+    oAt, oBt, ona2, onb2 = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, c["k"], "bf16")
+    assert _col_rel(At, oAt) < TOL_SKETCH and _col_rel(Bt, oBt) < TOL_SKETCH
+    assert np.allclose(na2, ona2, rtol=1e-6, atol=0)
+    assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
+
+
 def test_sketch_bf16_scalar_path_zero_column_and_b_is_a(api, ctx):
     d, n1, n2, k = 700, 45, 33, 21
     A, B, _, _ = latent(d, n1, n2)
