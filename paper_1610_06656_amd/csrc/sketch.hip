@@ -318,7 +318,8 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   auto launch = [&](KernelPtr kern, int64_t r0, int64_t nrows, int splits, int64_t rps, int s_base) {
     g.row0 = r0;
     // stored Pi: the launch's first row r0 is a whole number of 32-row blocks past row0
-    g.pi = pl.pi_stored ? static_cast<const char *>(pi_buf) + (size_t)((r0 - row0) / 32) * pl.mt_total * 1024
+    g.pi = pl.pi_stored ? static_cast<const char *>(pi_buf) +
+                              (size_t)((r0 - row0) / pl.pi_rows) * pl.mt_total * pl.pi_frag_bytes
                         : nullptr;
     g.rows = nrows;
     g.S = splits;
@@ -375,6 +376,18 @@ hipError_t sketch_finish(const SketchPlan &pl, const float *part, const double *
   hipLaunchKernelGGL(sketch_finish_kernel, dim3(bx, gy), dim3(256), 0, st, part, npart, S, ntot, n1, k, pl.kpad,
                      1.0 / std::sqrt((double)k), At, Bt, na2, nb2);
   return hipGetLastError();
+}
+
+size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows) {
+  if (!pl.pi_stored || rows <= 0) return 0;
+  return (size_t)((rows + pl.pi_rows - 1) / pl.pi_rows) * (size_t)pl.mt_total * (size_t)pl.pi_frag_bytes;
+}
+
+hipError_t pi_store(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
+                    hipStream_t st) {
+  if (!pl.pi_stored || rows <= 0) return hipSuccess;
+  return pl.prec == SMP_PREC_FP8 ? pi_store_fp8(pl, seed, r0, rows, k, buf, st)
+                                 : pi_store_bf16(pl, seed, r0, rows, k, buf, st);
 }
 
 hipError_t pi_fill(int64_t l0, int64_t nrows, int k, uint64_t seed, float *out, hipStream_t st) {

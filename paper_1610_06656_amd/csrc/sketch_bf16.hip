@@ -684,6 +684,8 @@ SketchPlan sketch_plan_bf16(int k) {
   SketchPlan p{};
   p.prec = SMP_PREC_BF16;
   p.pi_stored = 1;
+  p.pi_rows = kStep;
+  p.pi_frag_bytes = kPiUnit * 16;
   p.mt_total = (k + 15) / 16;
   p.nv = nv;
   p.waves = waves;
@@ -698,14 +700,8 @@ SketchPlan sketch_plan_bf16(int k) {
   return p;
 }
 
-size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows) {
-  if (!pl.pi_stored || rows <= 0) return 0;
-  return (size_t)((rows + kStep - 1) / kStep) * (size_t)pl.mt_total * (kPiUnit * 16);
-}
-
-hipError_t pi_store(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
-                    hipStream_t st) {
-  if (!pl.pi_stored || rows <= 0) return hipSuccess;
+hipError_t pi_store_bf16(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
+                         hipStream_t st) {
   const int64_t frags = (rows + kStep - 1) / kStep * pl.mt_total;
   const int64_t grid = (frags * 16 + 255) / 256;
   hipLaunchKernelGGL(pi_store_bf16_kernel, dim3((unsigned)grid), dim3(256), 0, st, seed, r0, rows, k, pl.mt_total,

@@ -141,7 +141,8 @@ __device__ __forceinline__ int scale_exp(float amax) {
 // travel in one 32-bit word per exchange.
 template <int NV, bool NORM, bool CLAMP>
 __device__ __forceinline__ void prep_block(const Row8<NV> (&x)[32], int64_t row, int64_t row_last, int g,
-                                           v8i (&b)[NV], int (&sb)[NV], float (&ksum)[NV], float (&kcmp)[NV]) {
+                                           v8i (&b)[NV], int (&sb)[NV], float (&ksum)[NV], float (&kcmp)[NV],
+                                           bool valid = true) {
   static_assert(NV <= 2, "exponent packing holds two columns");
   uint32_t pk = 0;   // byte 2v + h: biased exponent of half h of column v
 #pragma unroll
@@ -154,7 +155,7 @@ __device__ __forceinline__ void prep_block(const Row8<NV> (&x)[32], int64_t row,
       else a1 = __builtin_fmaxf(a1, __builtin_fabsf(xv));
       if constexpr (NORM) s2 = __builtin_fmaf(xv, xv, s2);
     }
-    if constexpr (NORM) kahan_add(ksum[v], kcmp[v], s2);
+    if constexpr (NORM) kahan_add(ksum[v], kcmp[v], valid ? s2 : 0.0f);
     pk |= (uint32_t)(scale_exp(a0) + 127) << (16 * v);
     pk |= (uint32_t)(scale_exp(a1) + 127) << (16 * v + 8);
   }
@@ -282,6 +283,182 @@ __global__ __launch_bounds__(512) void sketch_fp8_kernel(SkArgs g) {
   sk_epilogue<MT, NV>(g, w, col, c0, gq, acc, ksum, kcmp);
 }
 
+// ---------------------------------------------------------------------------
+// Stored-Pi variant (as for BF16): Pi is drawn once per push, rounded to
+// E4M3, into fragments of the A operand of one MFMA: 128-byte unit
+// (b * mt_total + i) * 16 + ... holds, for lane t = 16 g + q, the 32 bytes of
+// sketch row 16 i + q at the data rows 128 b + 16 g + (0..15) and
+// 128 b + 64 + 16 g + (0..15) (b: 128-row block from the push's first row);
+// a fragment is 2 KiB. Each workgroup (8 waves) then owns 16*8*NV columns and a
+// chunk of up to MT m-tiles; per 128-row step every lane loads its 32 rows x NV
+// columns and each wave copies its share of the chunk's fragments, one step
+// ahead, into registers; the fragments go to LDS and the rows are
+// scaled and converted after the step's MFMAs. The steady-state loop has no
+// data-dependent branches (see the BF16 stored-Pi pass).
+typedef uint32_t v4u8 __attribute__((ext_vector_type(4)));
+constexpr int kPiUnit8 = 128;   // 16-byte units per 2 KiB fragment
+
+__global__ __launch_bounds__(256) void pi_store_fp8_kernel(uint64_t seed, int64_t r0, int64_t nrows, int k,
+                                                           int mt_total, int64_t frags, v4u8 *__restrict__ out) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (u >= frags * 16) return;
+  const int64_t frag = u >> 4;
+  const int sub = (int)(u & 15);
+  const int g = sub >> 2, q4 = sub & 3;
+  const int i = (int)(frag % mt_total);
+  const int64_t blk = frag / mt_total;
+  const int c = 16 * i + 4 * q4;
+  float z[32][4];
+#pragma unroll
+  for (int e = 0; e < 32; ++e) {
+    const int64_t l = 128 * blk + 16 * g + (e < 16 ? e : e + 48);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (l < nrows && c < k) v = normals4(stream_call(seed, kTagPi, (uint64_t)(r0 + l), (uint32_t)(c >> 2)));
+    z[e][0] = v.x;
+    z[e][1] = c + 1 < k ? v.y : 0.f;
+    z[e][2] = c + 2 < k ? v.z : 0.f;
+    z[e][3] = c + 3 < k ? v.w : 0.f;
+  }
+  v4u8 *dst = out + frag * kPiUnit8 + 2 * (16 * g + 4 * q4);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t dw[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) dw[m] = (uint32_t)cvt4(z[4 * m][j], z[4 * m + 1][j], z[4 * m + 2][j], z[4 * m + 3][j]);
+    dst[2 * j] = v4u8{dw[0], dw[1], dw[2], dw[3]};
+    dst[2 * j + 1] = v4u8{dw[4], dw[5], dw[6], dw[7]};
+  }
+}
+
+template <int MT, int NV, bool VEC, bool CLAMP, bool NORM, int D>
+__device__ __forceinline__ void loop_fp8_stored(const SkArgs &g, const SkWork &w, int64_t col, int i0, int mv,
+                                                v4u8 *L, v4f (&acc)[MT][NV], float (&ksum)[NV], float (&kcmp)[NV]) {
+  constexpr int W = 8;
+  constexpr int CPW = (MT + W - 1) / W;
+  constexpr int LT = CPW * W;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int q = lane & 15, gq = lane >> 4;
+  const int64_t row_last = w.lend - 1;
+  const int64_t lcol = VEC ? (col < w.n - NV ? col : w.n - NV) : col;
+  const float *base = w.X + w.lbeg * w.ld;
+  const uint32_t ld = (uint32_t)w.ld;
+  const uint32_t lane_off = (uint32_t)(16 * gq) * ld + (uint32_t)lcol;
+  const int64_t nrows = w.lend - w.lbeg;
+  const v4u8 *pi = reinterpret_cast<const v4u8 *>(g.pi) + (int64_t)i0 * kPiUnit8 + 2 * lane;
+  const int64_t fstride = (int64_t)g.mt_total * kPiUnit8;
+  const int64_t blk0 = w.lbeg / KP8;
+  const int64_t nsteps = (nrows + KP8 - 1) / KP8;
+
+  Row8<NV> raw[D][32];
+  v4u8 pst[D][CPW][2];
+  v8i b[NV];
+  int sb[NV];
+  auto issue = [&](int set, int64_t t) {   // t < nsteps; every load is unconditional
+    load_block<NV, VEC, CLAMP>(w, base, lane_off, ld, nrows, KP8 * t, gq, lcol, raw[set]);
+    const v4u8 *src = pi + (blk0 + t) * fstride;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int i = wave + W * j;
+      const v4u8 *f = src + (i < mv ? i : mv - 1) * kPiUnit8;
+      pst[set][j][0] = f[0];
+      pst[set][j][1] = f[1];
+    }
+  };
+  auto land = [&](int set, int64_t t) {   // Pi of step t into LDS buffer t % 2, its rows from register set `set`
+    const bool valid = t < nsteps;
+    v4u8 *Ld = L + (t & 1) * (LT * kPiUnit8);
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int i = wave + W * j;
+      const bool keep = valid && i < mv;
+      Ld[i * kPiUnit8 + 2 * lane] = keep ? pst[set][j][0] : v4u8{0u, 0u, 0u, 0u};
+      Ld[i * kPiUnit8 + 2 * lane + 1] = keep ? pst[set][j][1] : v4u8{0u, 0u, 0u, 0u};
+    }
+    prep_block<NV, NORM, CLAMP>(raw[set], w.lbeg + KP8 * t + 16 * gq, row_last, gq, b, sb, ksum, kcmp, valid);
+  };
+  // fragments read from LDS two m-tiles at a time, the next pair issued before
+  // this pair's MFMAs (all MT at once would hold 8 MT registers)
+  auto frag = [&](const v4u8 *Lc, int i) {
+    const v4u8 lo = Lc[i * kPiUnit8 + 2 * lane], hi = Lc[i * kPiUnit8 + 2 * lane + 1];
+    return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+  };
+  auto multiply = [&](const v4u8 *Lc) {
+    constexpr int G = 2, NG = (MT + G - 1) / G;
+    v8i a[2][G];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < MT) a[0][j] = frag(Lc, j);
+#pragma unroll
+    for (int gr = 0; gr < NG; ++gr) {
+      if (gr + 1 < NG) {
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+          if ((gr + 1) * G + j < MT) a[(gr + 1) & 1][j] = frag(Lc, (gr + 1) * G + j);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int i = gr * G + j;
+        if (i < MT) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            acc[i][v] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[gr & 1][j], b[v], acc[i][v], 0, 0, 0, 127,
+                                                                         0, sb[v]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+#pragma unroll
+  for (int d = 0; d < D; ++d) issue(d, d < nsteps ? d : nsteps - 1);
+  land(0, 0);
+  for (int64_t t0 = 0; t0 < nsteps; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int64_t t = t0 + d;
+      __syncthreads();   // step t's fragments are in LDS buffer t % 2; buffer (t + 1) % 2 is no longer read
+      issue(d, t + D < nsteps ? t + D : nsteps - 1);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply(L + (t & 1) * (LT * kPiUnit8));
+      __builtin_amdgcn_sched_barrier(0);
+      land((d + 1) % D, t + 1);
+    }
+  }
+}
+
+template <int MT, int NV, bool VEC, bool CLAMP>
+__global__ __launch_bounds__(512) void sketch_fp8_stored_kernel(SkArgs g) {
+  constexpr int D = 1;   // one 128-row step of loads in flight
+  constexpr int LT = (MT + 7) / 8 * 8;
+  __shared__ __attribute__((aligned(16))) v4u8 L[2 * LT * kPiUnit8];
+
+  SkWork w;
+  if (!sk_decode(g, w)) return;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int q = lane & 15, gq = lane >> 4;
+  const int64_t col = (int64_t)w.tile * (16 * 8 * NV) + wave * (16 * NV) + q * NV;
+  const int i0 = w.kc * MT;
+  const int mv = g.mt_total - i0 < MT ? g.mt_total - i0 : MT;
+
+  v4f acc[MT][NV];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[i][v] = v4f{0.f, 0.f, 0.f, 0.f};
+  float ksum[NV], kcmp[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ksum[v] = kcmp[v] = 0.0f;
+
+  if (w.lbeg < w.lend) {
+    if (w.kc == 0) loop_fp8_stored<MT, NV, VEC, CLAMP, true, D>(g, w, col, i0, mv, L, acc, ksum, kcmp);
+    else loop_fp8_stored<MT, NV, VEC, CLAMP, false, D>(g, w, col, i0, mv, L, acc, ksum, kcmp);
+  }
+  sk_epilogue<MT, NV>(g, w, col, i0 * 16, gq, acc, ksum, kcmp);
+}
+
 using KernelPtr = void (*)(SkArgs);
 
 template <int NV, int MT>
@@ -318,6 +495,33 @@ Shape8 *shapes8(int &count) {
   return tabs;
 }
 
+template <int NV, int MT>
+struct KTab8S {
+  static void fill(KernelPtr *t, KernelPtr *tc, KernelPtr *ts) {
+    t[MT] = sketch_fp8_stored_kernel<MT, NV, true, false>;
+    tc[MT] = sketch_fp8_stored_kernel<MT, NV, true, true>;
+    ts[MT] = sketch_fp8_stored_kernel<MT, NV, false, true>;
+    KTab8S<NV, MT - 1>::fill(t, tc, ts);
+  }
+};
+template <int NV>
+struct KTab8S<NV, 0> {
+  static void fill(KernelPtr *, KernelPtr *, KernelPtr *) {}
+};
+
+constexpr int kStoredMaxMt8 = 13;
+
+KernelPtr fp8_stored_kernel_for(int mt, int variant) {
+  static KernelPtr t[kStoredMaxMt8 + 1], tc[kStoredMaxMt8 + 1], ts[kStoredMaxMt8 + 1];
+  static const bool init = [] {
+    KTab8S<1, kStoredMaxMt8>::fill(t, tc, ts);
+    return true;
+  }();
+  (void)init;
+  if (mt < 1 || mt > kStoredMaxMt8) return nullptr;
+  return variant == 0 ? t[mt] : variant == 1 ? tc[mt] : ts[mt];
+}
+
 // variant 0: vector loads over whole blocks; 1: vector loads, clamped; 2: scalar loads, clamped
 KernelPtr fp8_kernel_for(int nv, int mt, int variant) {
   int count = 0;
@@ -330,9 +534,9 @@ KernelPtr fp8_kernel_for(int nv, int mt, int variant) {
 
 }  // namespace
 
-// Tile: 8 waves x 16 x nv columns, at most `cap` m-tiles per workgroup.
-// SMP_SKETCH_TILE_FP8="nv,mt" overrides it (tuning sweeps).
-SketchPlan sketch_plan_fp8(int k) {
+// Regenerating pass: 8 waves x 16 x nv columns, at most `cap` m-tiles per
+// workgroup. SMP_SKETCH_TILE_FP8="nv,mt" overrides the tile (tuning sweeps).
+static SketchPlan sketch_plan_fp8_regen(int k) {
   SketchPlan p{};
   p.prec = SMP_PREC_FP8;
   p.mt_total = (k + 15) / 16;
@@ -355,6 +559,40 @@ SketchPlan sketch_plan_fp8(int k) {
   p.kernel_clamp = reinterpret_cast<void *>(fp8_kernel_for(nv, p.mt, 1));
   p.kernel_scalar = reinterpret_cast<void *>(fp8_kernel_for(nv, p.mt, 2));
   return p;
+}
+
+// Stored-Pi pass (the default): 128-column tiles (one column per lane), up to
+// 13 m-tiles per workgroup. SMP_SKETCH_FP8_STORED=0 selects the regenerating
+// pass above.
+SketchPlan sketch_plan_fp8(int k) {
+  if (const char *e = getenv("SMP_SKETCH_FP8_STORED"))
+    if (e[0] == '0' && e[1] == 0) return sketch_plan_fp8_regen(k);
+  SketchPlan p{};
+  p.prec = SMP_PREC_FP8;
+  p.pi_stored = 1;
+  p.pi_rows = KP8;
+  p.pi_frag_bytes = kPiUnit8 * 16;
+  p.mt_total = (k + 15) / 16;
+  p.nv = 1;
+  p.waves = 8;
+  p.kc = KP8;
+  p.kt = (p.mt_total + kStoredMaxMt8 - 1) / kStoredMaxMt8;
+  p.mt = (p.mt_total + p.kt - 1) / p.kt;
+  p.ncol_tile = 16 * 8;
+  p.kpad = p.mt_total * 16;
+  p.kernel = reinterpret_cast<void *>(fp8_stored_kernel_for(p.mt, 0));
+  p.kernel_clamp = reinterpret_cast<void *>(fp8_stored_kernel_for(p.mt, 1));
+  p.kernel_scalar = reinterpret_cast<void *>(fp8_stored_kernel_for(p.mt, 2));
+  return p;
+}
+
+hipError_t pi_store_fp8(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
+                        hipStream_t st) {
+  const int64_t frags = (rows + KP8 - 1) / KP8 * pl.mt_total;
+  const int64_t grid = (frags * 16 + 255) / 256;
+  hipLaunchKernelGGL(pi_store_fp8_kernel, dim3((unsigned)grid), dim3(256), 0, st, seed, r0, rows, k, pl.mt_total,
+                     frags, static_cast<v4u8 *>(buf));
+  return hipGetLastError();
 }
 
 }  // namespace smp

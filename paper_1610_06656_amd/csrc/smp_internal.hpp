@@ -39,7 +39,9 @@ struct SketchPlan {
   void *kernel;         // the instantiated kernel for this shape
   void *kernel_clamp;   // BF16, FP8: variant for partial blocks (the tail launch), else null
   void *kernel_scalar;  // BF16, FP8: variant with guarded scalar loads (unaligned or ragged inputs), else null
-  int pi_stored;        // 1: Pi is drawn once per push into a buffer that the pass streams (BF16)
+  int pi_stored;        // 1: Pi is drawn once per push into a buffer that the pass streams
+  int pi_rows;          // stored Pi: data rows per fragment block (32 BF16, 128 FP8)
+  int pi_frag_bytes;    // stored Pi: bytes of one fragment (one MFMA A operand: 1024 BF16, 2048 FP8)
 };
 
 // Partial-sketch slots a pass with S splits writes: S, plus one for the rows
@@ -55,6 +57,10 @@ SketchPlan sketch_plan_fp8(int k);
 // pl.pi_stored), and the kernel that fills it for rows [r0, r0 + rows).
 size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows);
 hipError_t pi_store(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf, hipStream_t st);
+hipError_t pi_store_bf16(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
+                         hipStream_t st);
+hipError_t pi_store_fp8(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
+                        hipStream_t st);
 
 // Workgroups of the plan's kernel that the device runs at once
 // (CUs x resident workgroups per CU).

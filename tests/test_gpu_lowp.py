@@ -277,6 +277,23 @@ def test_sketch_fp8_parity(api, ctx, name):
     assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("name", ["c1", "ragged", "k400_tiles"])
+def test_sketch_fp8_regenerating_pass_parity(api, ctx, name, monkeypatch):
+    """The FP8 pass that regenerates Pi inside each workgroup (selected with
+    SMP_SKETCH_FP8_STORED=0; the default pass stores Pi once per push) meets the
+    same bar against the oracle."""
+    monkeypatch.setenv("SMP_SKETCH_FP8_STORED", "0")
+    c = FP8_CASES[name]
+    log(f"fp8 regenerating sketch {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=min(5, c["n1"], c["n2"]))
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], r=1, prec=api.SMP_PREC_FP8)
+    At, Bt, na2, nb2 = _sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"])
+    oAt, oBt, ona2, onb2 = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, c["k"], "fp8")
+    assert _col_rel(At, oAt) < TOL_FP8 and _col_rel(Bt, oBt) < TOL_FP8
+    assert np.allclose(na2, ona2, rtol=1e-6, atol=0)
+    assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
+
+
 def test_sketch_fp8_streaming_push_on_block_boundaries(api, ctx):
     d, n1, n2, k = 3000, 130, 70, 64
     A, B, Ad, Bd = latent(d, n1, n2)
