@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sketch-pass GB/s + MFMA util; solves/s & p99 latency, BF16 vs FP32 plain"
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0   # dense
+PEAK_FP8_MFMA_TFLOPS = 5000.0    # dense
 PEAK_HBM_GBPS = 8000.0
 CFG = dict(d=200_000, n1=2000, n2=2000, R=10, sigma=0.1, alpha=0.5, k=400, r=10, T=10)
 
@@ -282,6 +284,7 @@ def main():
     value = in_bytes / (ms_step / 1e3) / 1e9
     sk_bf16 = bf16["avg"]["sketch"]
     sk_fp32 = fp32["avg"]["sketch"]
+    sk_fp8 = fp8["avg"]["sketch"]
     flops = (2.0 * c["k"] + 4.0) * c["d"] * (c["n1"] + c["n2"])
     fp32_tflops = flops / (sk_fp32 / 1e3) / 1e12
     hbm_gbps = in_bytes / (sk_bf16 / 1e3) / 1e9
@@ -309,6 +312,8 @@ def main():
                      "traffic": recorded_traffic("sketch_bf16_c2_traffic"),
                      "kernel": "BF16 sketch pass: pi_store_bf16_kernel, then sketch_bf16_stored_kernel "
                                "(v_mfma_f32_16x16x32_bf16) main and tail launch, timed together",
+                     "mfma_tflops": round(flops / (sk_bf16 / 1e3) / 1e12, 2),
+                     "mfma_frac": round(flops / (sk_bf16 / 1e3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4),
                      "kernel_ms": round(sk_bf16, 4), "bytes_per_launch": in_bytes},
         "solves_per_s": round(1e3 / ms_step, 3),
         "latency_ms": {"p50": round(pct(bf16["lat"], 50), 4), "p99": round(pct(bf16["lat"], 99), 4)},
@@ -320,7 +325,14 @@ def main():
             "traffic": recorded_traffic("sketch_fp32_c2_traffic"),
             "kernel": "sketch_kernel (v_mfma_f32_16x16x4f32)", "kernel_ms": round(sk_fp32, 4),
             "flops_per_launch": flops}),
-        "fp8": leg_summary(fp8),
+        "fp8": dict(leg_summary(fp8), roofline={
+            "bound": "hbm", "achieved": round(in_bytes / (sk_fp8 / 1e3) / 1e9, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(in_bytes / (sk_fp8 / 1e3) / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
+            "kernel": "FP8 sketch pass: pi_store_fp8_kernel, then sketch_fp8_stored_kernel "
+                      "(v_mfma_scale_f32_16x16x128_f8f6f4) main and tail launch, timed together",
+            "kernel_ms": round(sk_fp8, 4), "bytes_per_launch": in_bytes,
+            "mfma_tflops": round(flops / (sk_fp8 / 1e3) / 1e12, 2),
+            "mfma_frac": round(flops / (sk_fp8 / 1e3) / 1e12 / PEAK_FP8_MFMA_TFLOPS, 4)}),
         "bf16_vs_fp32_solves": round(fp32["ms_step"] / bf16["ms_step"], 3),
     }
     if args.copy_calibration:
