@@ -93,7 +93,7 @@ typedef struct smp_params {
   uint32_t flags;     /* SMP_B_IS_A */
   double m;           /* sample-count parameter of Eq. (1); > 0 */
   uint64_t seed;      /* Philox key */
-  int32_t init_iters; /* subspace iterations of the WAltMin init; 0 = default (4) */
+  int32_t init_iters; /* subspace iterations of the WAltMin init; 0 = default (2) */
   int32_t reserved;   /* must be 0 */
 } smp_params;
 

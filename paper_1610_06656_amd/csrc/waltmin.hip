@@ -688,7 +688,7 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   const int64_t n1 = om.n1, n2 = om.n2;
   const int r = prm.r, T = prm.T;
   const int p = std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample)));
-  const int iters = prm.init_iters > 0 ? prm.init_iters : 4;
+  const int iters = prm.init_iters > 0 ? prm.init_iters : 2;
   const bool split = prm.omega_mode == SMP_OMEGA_SPLIT;
   Ws w = carve_ws(wsbase, n1, n2, p, r);
   const uint8_t *scsr = split ? om.sub_csr : nullptr;
