@@ -186,6 +186,18 @@ __global__ void apply_kernel(const double *X, int64_t n, int pin, const double *
 // Symmetric G (p x p) -> eigenvalues (descending) lam[p], eigenvectors W (p x p,
 // column c is the c-th eigenvector). One wave; cyclic Jacobi with the
 // round-robin pairing so the p/2 rotations of a round are disjoint.
+// An off-diagonal entry is negligible when it is at most 1e-15 of the geometric
+// mean of its two diagonal entries or 1e-17 of the largest diagonal magnitude;
+// negligible entries are not rotated, and the iteration stops at the first
+// sweep that finds none left (at most 40 sweeps). A test on the total
+// off-diagonal mass alone can stall when the eigenvalues span several decades:
+// every rotation leaves rounding errors of eps times the largest eigenvalue in
+// entries that only the small diagonal entries would have to outgrow.
+__device__ __forceinline__ bool jacobi_negligible(double apq, double app, double aqq, double dmax) {
+  const double a = fabs(apq);
+  return a <= 1e-15 * sqrt(fabs(app * aqq)) || a <= 1e-17 * dmax;
+}
+
 __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict__ G, int p, double *__restrict__ W,
                                                         double *__restrict__ lam) {
   __shared__ double A[kMaxP * kMaxP];
@@ -202,14 +214,14 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
   const int pe = (p + 1) & ~1;   // even number of players; index p is a dummy when p is odd
   const int half = pe / 2;
   for (int sweep = 0; sweep < 40 && p > 1; ++sweep) {
-    double off = 0.0, dia = 0.0;
+    double dmax = 0.0;
+    for (int a = 0; a < p; ++a) dmax = fmax(dmax, fabs(A[a * p + a]));
+    bool left = false;
     for (int e = t; e < p * p; e += 64) {
-      const double v = A[e];
-      if (e / p == e % p) dia += v * v; else off += v * v;
+      const int i = e / p, j = e % p;
+      if (i < j && !jacobi_negligible(A[e], A[i * p + i], A[j * p + j], dmax)) left = true;
     }
-    off = wave_sum(off);
-    dia = wave_sum(dia);
-    if (off <= 1e-32 * dia || dia == 0.0) break;
+    if (__ballot(left) == 0) break;
     for (int rd = 0; rd < pe - 1; ++rd) {
       if (t < half) {
         int P, Q;
@@ -224,7 +236,7 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
         double c = 1.0, s = 0.0;
         if (Q < p) {
           const double apq = A[P * p + Q];
-          if (apq != 0.0) {
+          if (!jacobi_negligible(apq, A[P * p + P], A[Q * p + Q], dmax)) {
             const double tau = (A[Q * p + Q] - A[P * p + P]) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
@@ -416,19 +428,29 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, i
 }
 
 // ---------------------------------------------------------------- weighted LS solves
+// Lane `src`'s value of v, in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // One workgroup (4 waves) per output row o; RT = ceil((r+1)/16) MFMA tiles per
 // side. Each wave takes every fourth chunk of 64 entries: the chunk's metadata
 // is loaded one entry per lane, then BATCH groups of four entries have their
-// rows of the fixed factor loaded together before their MFMAs. The four waves'
+// rows of the fixed factor loaded together before their MFMAs (a whole chunk
+// at once when RT = 1); the wave's next chunk's metadata is requested right
+// after the first batch of rows, so that the two loads overlap. The four waves'
 // Gram tiles are summed in LDS and the r x r system is solved there.
 template <int RT>
-__global__ __launch_bounds__(256) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+__global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                        const double *__restrict__ w, const double *__restrict__ mt,
                                                        const uint8_t *__restrict__ sub, int sel,
                                                        const double *__restrict__ Q, int r, int64_t n_out,
                                                        double *__restrict__ Xout) {
   constexpr int D = RT * 16;
-  constexpr int BATCH = RT == 3 ? 4 : 8;
+  constexpr int BATCH = RT == 1 ? 16 : (RT == 2 ? 8 : 4);
   __shared__ double Gw[4 * D * D];
   __shared__ double L[32 * 32];
   __shared__ double hv[32];
@@ -444,38 +466,83 @@ __global__ __launch_bounds__(256) void ls_solve_kernel(const int64_t *__restrict
     for (int b = 0; b < RT; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
   const int64_t e0 = ptr[o], e1 = ptr[o + 1];
-  for (int64_t eb = e0 + 64 * wave; eb < e1; eb += 256) {
+  // Every load below is unconditional (indices clamped into the row, values
+  // masked afterwards): with loads under conditions the compiler cannot count
+  // the ones in flight and waits for all of them, which would serialise the
+  // metadata prefetch with the rows.
+  const uint8_t *subp = sub ? sub : reinterpret_cast<const uint8_t *>(idx);   // any valid bytes when unused
+  struct Meta {
+    int32_t row;
+    double w, m;
+    uint8_t sb;
+    bool in;
+  };
+  auto issue_meta = [&](int64_t eb, Meta &x) {   // requires e1 > e0
     const int64_t me = eb + lt;
-    const bool ok = me < e1 && (!sub || sub[me] == sel);
-    const int32_t mrow = ok ? idx[me] : 0;
-    const double mw = ok ? w[me] : 0.0;
-    const double mm = ok ? mt[me] : 0.0;
-    const int nsteps = (int)std::min<int64_t>(16, (e1 - eb + 3) / 4);
-    for (int s0 = 0; s0 < nsteps; s0 += BATCH) {
-      double af[BATCH][RT], bf[BATCH][RT];
+    const int64_t mc = me < e1 ? me : e1 - 1;
+    x.in = me < e1;
+    x.row = idx[mc];
+    x.w = w[mc];
+    x.m = mt[mc];
+    x.sb = subp[mc];
+  };
+  // Rows of the fixed factor for the four-entry groups s0 .. s0 + BATCH - 1:
+  // the loads only (raw values); `multiply` masks them and runs the products.
+  struct Batch {
+    double qv[BATCH][RT];
+  };
+  auto gather = [&](int s0, int32_t mrow, Batch &bt) {
 #pragma unroll
-      for (int q = 0; q < BATCH; ++q) {
-        const int src = (4 * (s0 + q) + ent) & 63;
-        const int32_t row = __shfl(mrow, src, 64);
-        const double we = __shfl(mw, src, 64);
-        const double me_ = __shfl(mm, src, 64);
-        const bool live = s0 + q < nsteps && we != 0.0;
+    for (int q = 0; q < BATCH; ++q) {
+      const int32_t row = __shfl(mrow, (4 * (s0 + q) + ent) & 63, 64);
 #pragma unroll
-        for (int tt = 0; tt < RT; ++tt) {
-          const int a = tt * 16 + col;
-          double x = 0.0;
-          if (live) x = a < r ? Q[(int64_t)row * r + a] : (a == r ? me_ : 0.0);
-          bf[q][tt] = x;
-          af[q][tt] = a < r ? we * x : 0.0;
-        }
+      for (int tt = 0; tt < RT; ++tt) {
+        const int a = tt * 16 + col;
+        bt.qv[q][tt] = Q[(int64_t)row * r + (a < r ? a : r - 1)];
+      }
+    }
+  };
+  auto multiply = [&](int s0, int nsteps, double mw, double mm, const Batch &bt) {
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int src = (4 * (s0 + q) + ent) & 63;
+      const double we = __shfl(mw, src, 64);
+      const double me_ = __shfl(mm, src, 64);
+      const bool live = s0 + q < nsteps && we != 0.0;
+      double af[RT], bf[RT];
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt) {
+        const int a = tt * 16 + col;
+        const double x = live ? (a < r ? bt.qv[q][tt] : (a == r ? me_ : 0.0)) : 0.0;
+        bf[tt] = x;
+        af[tt] = a < r ? we * x : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < BATCH; ++q)
+      for (int ta = 0; ta < RT; ++ta)
 #pragma unroll
-        for (int ta = 0; ta < RT; ++ta)
-#pragma unroll
-          for (int tb = 0; tb < RT; ++tb)
-            acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q][ta], bf[q][tb], acc[ta][tb], 0, 0, 0);
+        for (int tb = 0; tb < RT; ++tb)
+          acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ta], bf[tb], acc[ta][tb], 0, 0, 0);
+    }
+  };
+  int64_t eb = e0 + 64 * wave;
+  if (eb < e1) {
+    Meta cur;
+    issue_meta(eb, cur);
+    for (; eb < e1; eb += 256) {
+      const bool ok = cur.in && (!sub || cur.sb == sel);
+      const int32_t mrow = ok ? cur.row : 0;
+      const double mw = ok ? cur.w : 0.0, mm = ok ? cur.m : 0.0;
+      const int nsteps = (int)std::min<int64_t>(16, (e1 - eb + 3) / 4);
+      Batch bt;
+      gather(0, mrow, bt);
+      issue_meta(eb + 256, cur);   // the wave's next chunk, requested after this chunk's first rows
+      __builtin_amdgcn_sched_barrier(0);   // all of the batch's loads in flight before the first product
+      multiply(0, nsteps, mw, mm, bt);
+      for (int s0 = BATCH; s0 < nsteps; s0 += BATCH) {
+        gather(s0, mrow, bt);
+        __builtin_amdgcn_sched_barrier(0);
+        multiply(s0, nsteps, mw, mm, bt);
+      }
     }
   }
   // v_mfma_f64_16x16x4f64 leaves D[4*j + t/16][t%16] in register j of lane t
@@ -499,6 +566,64 @@ __global__ __launch_bounds__(256) void ls_solve_kernel(const int64_t *__restrict
   for (int a = 0; a < r; ++a) {
     mx = fmax(mx, G[a * D + a]);
     tr += G[a * D + a];
+  }
+  if constexpr (RT == 1) {
+    // r <= 15: the same steps with row i of the system in the registers of
+    // lane i (pivots and solution entries broadcast with v_readlane); the
+    // back substitution reads the columns of L through LDS once.
+    double l[D], Lc[D];
+    bool solved = false;
+    double x = 0.0;
+    for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
+      const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
+      const double tol = 1e-12 * (mx + shift);
+#pragma unroll
+      for (int k = 0; k < D; ++k) l[k] = (t < r && k < r) ? G[t * D + k] + (k == t ? shift : 0.0) : 0.0;
+      double y = t < r ? G[t * D + r] : 0.0;
+      bool ok = true;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        if (j < r && ok) {
+          const double piv = readlane_f64(l[j], j);
+          if (!(piv > tol)) {
+            ok = false;
+          } else {
+            const double d = sqrt(piv);
+            l[j] = t == j ? d : (t > j ? l[j] / d : l[j]);
+#pragma unroll
+            for (int k = j + 1; k < D; ++k)
+              if (k < r) l[k] -= l[j] * readlane_f64(l[j], k);   // only k <= t is kept in lane t
+          }
+        }
+      }
+      if (!ok) continue;
+      // forward: L y = h
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        if (k < r) {
+          const double yk = readlane_f64(y, k) / readlane_f64(l[k], k);
+          y = t == k ? yk : (t > k ? y - l[k] * yk : y);
+        }
+      }
+      // backward: L^T x = y; lane t needs column t of L
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        if (t < r && k <= t) L[t * 32 + k] = l[k];
+      wsync();
+#pragma unroll
+      for (int k = 0; k < D; ++k) Lc[k] = (k < r && k > t) ? L[k * 32 + t] : 0.0;
+#pragma unroll
+      for (int k = D - 1; k >= 0; --k) {
+        if (k < r) {
+          const double xk = readlane_f64(y, k) / readlane_f64(l[k], k);
+          y = t == k ? xk : (t < k ? y - Lc[k] * xk : y);
+        }
+      }
+      x = y;
+      solved = true;
+    }
+    if (t < r) Xout[o * r + t] = solved ? x : 0.0;
+    return;
   }
   bool solved = false;
   for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
