@@ -51,41 +51,71 @@ constexpr int kInitOversample = 10;
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)std::max<int64_t>(1, (a + b - 1) / b); }
 
 // ---------------------------------------------------------------- Gram
-// part[b][a*p + c] = sum over the rows of block b of X[i][a] X[i][c]. Thread t
-// owns the entries t, t+256, ... of the p x p result; rows are staged in LDS.
+// part[b][a*p + c] = sum over the rows of block b of X[i][a] X[i][c], on the
+// FP64 matrix cores: wave w of the block takes the row quads w, w + 4, ...
+// (four at a time); lane (c, e) = (lane % 16, lane / 16) loads
+// X[4 quad + e][16 tt + c], which is both the A and the B fragment of
+// v_mfma_f64_16x16x4f64 for the RT x RT tiles of the result. Rows past the
+// block and columns past p load a clamped in-range element and are masked to
+// zero afterwards (unconditional loads keep several quads in flight). The four
+// waves' tiles are summed in LDS in a fixed order (wave 3, then 2, 1, 0).
+template <int RT>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const double *__restrict__ X, int64_t n, int p,
                                                            int64_t rows_per_block, double *__restrict__ part) {
-  __shared__ double rows[32 * kMaxP];
-  const int t = threadIdx.x;
-  const int pp = p * p;
-  int ia[16], ib[16];
-  double acc[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int idx = t + 256 * u;
-    ia[u] = idx < pp ? idx / p : 0;
-    ib[u] = idx < pp ? idx % p : 0;
-    acc[u] = 0.0;
-  }
+  constexpr int D = 16 * RT;
+  constexpr int B = 4;
+  __shared__ double S[D * D];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int c = lane & 15, e = lane >> 4;
   const int64_t r0 = blockIdx.x * rows_per_block;
   const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_block);
-  for (int64_t base = r0; base < r1; base += 32) {
-    const int nr = (int)std::min<int64_t>(32, r1 - base);
-    for (int e = t; e < nr * p; e += 256) rows[e] = X[base * p + e];
-    __syncthreads();
-    for (int rr = 0; rr < nr; ++rr) {
-      const double *row = rows + rr * p;
+  v4d acc[RT][RT];
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (t + 256 * u < pp) acc[u] = fma(row[ia[u]], row[ib[u]], acc[u]);
+  for (int ta = 0; ta < RT; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < RT; ++tb) acc[ta][tb] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t nq = (r1 - r0 + 3) / 4;
+  for (int64_t q0 = wave; q0 < nq; q0 += 4 * B) {
+    double x[B][RT];
+#pragma unroll
+    for (int bq = 0; bq < B; ++bq) {
+      const int64_t row = r0 + 4 * (q0 + 4 * bq) + e;
+      const int64_t rc = row < r1 ? row : r1 - 1;
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt) {
+        const int col = 16 * tt + c;
+        x[bq][tt] = X[rc * p + (col < p ? col : p - 1)];
+      }
+    }
+#pragma unroll
+    for (int bq = 0; bq < B; ++bq) {
+      const bool live = r0 + 4 * (q0 + 4 * bq) + e < r1;
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt) x[bq][tt] = (live && 16 * tt + c < p) ? x[bq][tt] : 0.0;
+#pragma unroll
+      for (int ta = 0; ta < RT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < RT; ++tb)
+          acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bq][ta], x[bq][tb], acc[ta][tb], 0, 0, 0);
+    }
+  }
+  // register j of lane (c, e) holds entry (16 ta + 4 j + e, 16 tb + c)
+  for (int w = 3; w >= 0; --w) {
+    if (wave == w) {
+#pragma unroll
+      for (int ta = 0; ta < RT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < RT; ++tb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            double *q = S + (16 * ta + 4 * j + e) * D + 16 * tb + c;
+            *q = w == 3 ? acc[ta][tb][j] : *q + acc[ta][tb][j];
+          }
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int idx = t + 256 * u;
-    if (idx < pp) part[(int64_t)blockIdx.x * pp + idx] = acc[u];
-  }
+  const int pp = p * p;
+  for (int idx = t; idx < pp; idx += 256) part[(int64_t)blockIdx.x * pp + idx] = S[(idx / p) * D + idx % p];
 }
 
 __global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, int p, double *__restrict__ G) {
@@ -184,7 +214,7 @@ __global__ void apply_kernel(const double *X, int64_t n, int pin, const double *
 
 // ---------------------------------------------------------------- Jacobi eigen
 // Symmetric G (p x p) -> eigenvalues (descending) lam[p], eigenvectors W (p x p,
-// column c is the c-th eigenvector). One wave; cyclic Jacobi with the
+// column c is the c-th eigenvector). One workgroup; cyclic Jacobi with the
 // round-robin pairing so the p/2 rotations of a round are disjoint.
 // An off-diagonal entry is negligible when it is at most 1e-15 of the geometric
 // mean of its two diagonal entries or 1e-17 of the largest diagonal magnitude;
@@ -198,15 +228,17 @@ __device__ __forceinline__ bool jacobi_negligible(double apq, double app, double
   return a <= 1e-15 * sqrt(fabs(app * aqq)) || a <= 1e-17 * dmax;
 }
 
-__global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict__ G, int p, double *__restrict__ W,
+template <int NT>
+__global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict__ G, int p, double *__restrict__ W,
                                                         double *__restrict__ lam) {
   __shared__ double A[kMaxP * kMaxP];
   __shared__ double V[kMaxP * kMaxP];
   __shared__ double cs[kMaxP / 2][2];
   __shared__ int pr[kMaxP / 2][2];
   __shared__ double red[64];
+  __shared__ int any_left;
   const int t = threadIdx.x;
-  for (int e = t; e < p * p; e += 64) {
+  for (int e = t; e < p * p; e += NT) {
     A[e] = 0.5 * (G[e] + G[(e % p) * p + e / p]);
     V[e] = (e / p == e % p) ? 1.0 : 0.0;
   }
@@ -216,12 +248,14 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
   for (int sweep = 0; sweep < 40 && p > 1; ++sweep) {
     double dmax = 0.0;
     for (int a = 0; a < p; ++a) dmax = fmax(dmax, fabs(A[a * p + a]));
-    bool left = false;
-    for (int e = t; e < p * p; e += 64) {
+    if (t == 0) any_left = 0;
+    __syncthreads();
+    for (int e = t; e < p * p; e += NT) {
       const int i = e / p, j = e % p;
-      if (i < j && !jacobi_negligible(A[e], A[i * p + i], A[j * p + j], dmax)) left = true;
+      if (i < j && !jacobi_negligible(A[e], A[i * p + i], A[j * p + j], dmax)) any_left = 1;
     }
-    if (__ballot(left) == 0) break;
+    __syncthreads();
+    if (any_left == 0) break;
     for (int rd = 0; rd < pe - 1; ++rd) {
       if (t < half) {
         int P, Q;
@@ -250,7 +284,7 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int e = t; e < half * p; e += 64) {
+      for (int e = t; e < half * p; e += NT) {
         const int pi = e / p, i = e % p;
         const int P = pr[pi][0], Q = pr[pi][1];
         if (Q < p) {
@@ -265,7 +299,7 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int e = t; e < half * p; e += 64) {
+      for (int e = t; e < half * p; e += NT) {
         const int pi = e / p, j = e % p;
         const int P = pr[pi][0], Q = pr[pi][1];
         if (Q < p) {
@@ -290,10 +324,21 @@ __global__ __launch_bounds__(64) void jacobi_eig_kernel(const double *__restrict
     red[rank] = (double)t;
   }
   __syncthreads();
-  for (int e = t; e < p * p; e += 64) {
+  for (int e = t; e < p * p; e += NT) {
     const int i = e / p, a = e % p;
     W[e] = V[i * p + (int)red[a]];
   }
+}
+
+// The rounds are latency-bound chains (rotation, then the column and row
+// updates); more threads shorten the update phases of the larger problems.
+void jacobi_eig(const double *G, int p, double *W, double *lam, hipStream_t st) {
+  if (p <= 16)
+    hipLaunchKernelGGL(jacobi_eig_kernel<64>, dim3(1), dim3(64), 0, st, G, p, W, lam);
+  else if (p <= 32)
+    hipLaunchKernelGGL(jacobi_eig_kernel<256>, dim3(1), dim3(256), 0, st, G, p, W, lam);
+  else
+    hipLaunchKernelGGL(jacobi_eig_kernel<1024>, dim3(1), dim3(1024), 0, st, G, p, W, lam);
 }
 
 // From the eigenpairs of a Gram matrix, build the maps of a Rayleigh-Ritz /
@@ -732,7 +777,15 @@ size_t carve_bytes(int64_t n1, int64_t n2, int p, int r) {
 int gram(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
   const int nblk = (int)std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + 63) / 64));
   const int64_t rpb = (n + nblk - 1) / nblk;
-  hipLaunchKernelGGL(gram_partial_kernel, dim3(nblk), dim3(256), 0, st, X, n, p, rpb, w.part);
+  const dim3 grid((unsigned)nblk), blk(256);
+  if (p <= 16)
+    hipLaunchKernelGGL(gram_partial_kernel<1>, grid, blk, 0, st, X, n, p, rpb, w.part);
+  else if (p <= 32)
+    hipLaunchKernelGGL(gram_partial_kernel<2>, grid, blk, 0, st, X, n, p, rpb, w.part);
+  else if (p <= 48)
+    hipLaunchKernelGGL(gram_partial_kernel<3>, grid, blk, 0, st, X, n, p, rpb, w.part);
+  else
+    hipLaunchKernelGGL(gram_partial_kernel<4>, grid, blk, 0, st, X, n, p, rpb, w.part);
   return nblk;
 }
 
@@ -794,7 +847,7 @@ void ls_solve(const int64_t *ptr, const int32_t *idx, const double *wt, const do
 void canonical(const Ws &w, const double *U, int64_t n1, const double *V, int64_t n2, int r, double *Uout,
                double *Vout, double *sigma, hipStream_t st) {
   gram_full(w, U, n1, r, st);
-  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(64), 0, st, w.G, r, w.W, w.lam);
+  jacobi_eig(w.G, r, w.W, w.lam, st);
   hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, r, r, w.Mu, w.Mv, sigma);
   apply(U, n1, r, w.Mu, r, Uout, st);
   apply(V, n2, r, w.Mv, r, Vout, st);
@@ -835,7 +888,7 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
   // Rayleigh-Ritz: X = R Y; X^T X = W diag(lam) W^T; U0 = X W_r lam^-1/2, V0 = Y W_r
   gram_full(w, w.X, n1, p, st);
-  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(64), 0, st, w.G, p, w.W, w.lam);
+  jacobi_eig(w.G, p, w.W, w.lam, st);
   hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, p, r, w.Mu, w.Mv, w.sig);
   apply(w.X, n1, p, w.Mu, r, w.U, st);
   apply(w.Y, n2, p, w.Mv, r, w.V, st);
