@@ -118,13 +118,26 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const double *__restr
   for (int idx = t; idx < pp; idx += 256) part[(int64_t)blockIdx.x * pp + idx] = S[(idx / p) * D + idx % p];
 }
 
+// Entry idx of the sum of the nblk Gram partials, in block order; the loads of
+// 16 blocks are issued together (the partials were just written by another
+// kernel, so each round trip goes to memory).
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nblk, int pp, int idx) {
+  double sum = 0.0;
+  for (int b0 = 0; b0 < nblk; b0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(b0 + u < nblk ? b0 + u : nblk - 1) * pp + idx];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (b0 + u < nblk) sum += v[u];
+  }
+  return sum;
+}
+
 __global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, int p, double *__restrict__ G) {
   const int pp = p * p;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < pp; idx += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * pp + idx];
-    G[idx] = s;
-  }
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < pp; idx += gridDim.x * blockDim.x)
+    G[idx] = sum_partials(part, nblk, pp, idx);
 }
 
 // ---------------------------------------------------------------- Cholesky -> L^-T
@@ -140,16 +153,7 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict_
   __shared__ double dinv[kMaxP];
   const int t = threadIdx.x;
   const int pp = p * p;
-  for (int idx = t; idx < pp; idx += 256) {
-    // four independent partial sums keep several loads in flight
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    int b = 0;
-    for (; b + 4 <= nblk; b += 4)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) s4[u] += part[(int64_t)(b + u) * pp + idx];
-    for (; b < nblk; ++b) s4[0] += part[(int64_t)b * pp + idx];
-    L[idx] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-  }
+  for (int idx = t; idx < pp; idx += 256) L[idx] = sum_partials(part, nblk, pp, idx);
   __syncthreads();
   double tr = 0.0, mx = 0.0;
   for (int a = 0; a < p; ++a) {
@@ -365,8 +369,11 @@ __global__ void ritz_maps_kernel(const double *__restrict__ W, const double *__r
 // is given) of w_e M~_e Y[idx_e][a]. One workgroup (4 waves) per output row;
 // each wave takes every fourth chunk of 64 entries, loads the chunk's metadata
 // one entry per lane, and lets groups of G lanes (G >= p) take one entry each
-// and load its row of Y, 8 entries in flight per group. Partial sums are
-// combined with shuffles within a wave and through LDS across waves.
+// and load its row of Y, 16 entries in flight per group. The loads are
+// unconditional (clamped indices, values masked afterwards) and the wave's
+// next chunk's metadata is requested after the first batch of rows, so that
+// one memory round trip serves both. Partial sums are combined with shuffles
+// within a wave and through LDS across waves.
 template <int G>
 __global__ __launch_bounds__(256) void spmm_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                    const double *__restrict__ w, const double *__restrict__ mt,
@@ -381,24 +388,45 @@ __global__ __launch_bounds__(256) void spmm_kernel(const int64_t *__restrict__ p
   const int64_t o = blockIdx.x;
   if (o >= n_out) return;
   const int64_t e0 = ptr[o], e1 = ptr[o + 1];
+  const uint8_t *subp = sub ? sub : reinterpret_cast<const uint8_t *>(idx);   // any valid bytes when unused
+  constexpr int BATCH = 16;
   double acc = 0.0;
-  for (int64_t eb = e0 + 64 * wave; eb < e1; eb += 256) {
-    const int64_t me = eb + lane;
-    const bool ok = me < e1 && (!sub || sub[me] == sel);
-    const int32_t mj = ok ? idx[me] : 0;
-    const double mv = ok ? w[me] * mt[me] : 0.0;
-    const int cnt = (int)std::min<int64_t>(64, e1 - eb);
-    for (int u = 0; u < cnt; u += NG * 8) {
-      double y[8], v[8];
+  int64_t eb = e0 + 64 * wave;
+  if (eb < e1) {
+    int32_t cj;
+    double cw, cm;
+    uint8_t cs;
+    bool cin;
+    auto issue_meta = [&](int64_t ebx) {   // requires e1 > e0
+      const int64_t me = ebx + lane;
+      const int64_t mc = me < e1 ? me : e1 - 1;
+      cin = me < e1;
+      cj = idx[mc];
+      cw = w[mc];
+      cm = mt[mc];
+      cs = subp[mc];
+    };
+    issue_meta(eb);
+    for (; eb < e1; eb += 256) {
+      const bool ok = cin && (!sub || cs == sel);
+      const int32_t mj = ok ? cj : 0;
+      const double mv = ok ? cw * cm : 0.0;
+      // group g takes entries g, g + NG, g + 2 NG, ... of the chunk (G of them)
+      for (int u0 = 0; u0 < G; u0 += BATCH) {
+        double y[BATCH];
 #pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8) {
-        const int src = (u + s8 * NG + g) & 63;
-        const int j = __shfl(mj, src, 64);
-        v[s8] = __shfl(mv, src, 64);
-        y[s8] = (a < p && v[s8] != 0.0) ? Y[(int64_t)j * p + a] : 0.0;
+        for (int s8 = 0; s8 < BATCH; ++s8) {
+          const int j = __shfl(mj, ((u0 + s8) * NG + g) & 63, 64);
+          y[s8] = Y[(int64_t)j * p + (a < p ? a : p - 1)];
+        }
+        if (u0 == 0) issue_meta(eb + 256);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s8 = 0; s8 < BATCH; ++s8) {
+          const double v = __shfl(mv, ((u0 + s8) * NG + g) & 63, 64);
+          acc = fma(v, (a < p && v != 0.0) ? y[s8] : 0.0, acc);
+        }
       }
-#pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8) acc = fma(v[s8], y[s8], acc);
     }
   }
 #pragma unroll
@@ -775,7 +803,7 @@ size_t carve_bytes(int64_t n1, int64_t n2, int p, int r) {
 }
 
 int gram(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
-  const int nblk = (int)std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + 63) / 64));
+  const int nblk = (int)std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + 127) / 128));
   const int64_t rpb = (n + nblk - 1) / nblk;
   const dim3 grid((unsigned)nblk), blk(256);
   if (p <= 16)
