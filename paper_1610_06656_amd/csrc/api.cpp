@@ -390,6 +390,24 @@ smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t
   return SMP_OK;
 }
 
+// The sampler's scratch (per-entry probabilities alpha, beta, the F totals,
+// block sums and counts) in the context's buffer; carved the same way on every
+// call, so a fill pass can follow a count pass made by an earlier call.
+static smp_status sample_ws(smp_ctx *ctx, int64_t n1, int64_t n2, smp::SampleWs &ws) {
+  const int64_t nt = n1 + n2;
+  smp_ctx_bufs &b = bufs(ctx);
+  const size_t need = al(64) + al(n1 * 8) + al(n2 * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);
+  smp_status s = ensure(ctx, b.samplews, need);
+  if (s != SMP_OK) return s;
+  char *c = static_cast<char *>(b.samplews.p);
+  ws.stats = take<double>(c, 8);
+  ws.alpha = take<double>(c, n1);
+  ws.beta = take<double>(c, n2);
+  ws.blocks = take<double>(c, nt / 256 + 4);
+  ws.cnt = take<int64_t>(c, nt + 2);
+  return SMP_OK;
+}
+
 smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const float *nb2, smp_omega *om) {
   if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
   const std::string m = check(p);
@@ -401,18 +419,10 @@ smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const
   const bool split = p->omega_mode == SMP_OMEGA_SPLIT;
   if (split && om->cap > 0 && (!om->sub_csr || !om->sub_csc))
     return fail(ctx, SMP_ERR_INVALID_ARG, "SPLIT mode needs sub_csr and sub_csc");
-  const int64_t n1 = p->n1, n2 = p->n2, nt = n1 + n2;
-  smp_ctx_bufs &b = bufs(ctx);
-  const size_t need = al(64) + al(n1 * 8) + al(n2 * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);
-  smp_status s = ensure(ctx, b.samplews, need);
-  if (s != SMP_OK) return s;
-  char *c = static_cast<char *>(b.samplews.p);
+  const int64_t n1 = p->n1, n2 = p->n2;
   smp::SampleWs ws;
-  ws.stats = take<double>(c, 8);
-  ws.alpha = take<double>(c, n1);
-  ws.beta = take<double>(c, n2);
-  ws.blocks = take<double>(c, nt / 256 + 4);
-  ws.cnt = take<int64_t>(c, nt + 2);
+  smp_status s = sample_ws(ctx, n1, n2, ws);
+  if (s != SMP_OK) return s;
   SMP_HIP(ctx, smp::sample_prepare(na2, nb2, n1, n2, ws, ctx->stream));
   SMP_HIP(ctx, smp::sample_count(ws, n1, n2, p->m, p->seed, om->row_ptr, om->col_ptr, ws.cnt, ctx->stream));
   SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, om->row_ptr + n1, 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -523,8 +533,14 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
   om.mt_csc = take<double>(c, nnz);
   om.sub_csr = split ? take<uint8_t>(c, nnz) : nullptr;
   om.sub_csc = split ? take<uint8_t>(c, nnz) : nullptr;
-  s = smp_sample(ctx, &q, na2, nb2, &om);
-  if (s != SMP_OK) return s;
+  if (nnz > 0) {
+    // the counting call above left alpha, beta and the listings' pointers in
+    // place: only the fill pass remains
+    smp::SampleWs ws;
+    s = sample_ws(ctx, n1, n2, ws);
+    if (s != SMP_OK) return s;
+    SMP_HIP(ctx, smp::sample_fill(ws, n1, n2, q.m, q.seed, q.T, split ? 1 : 0, om, ctx->stream));
+  }
   mark(ctx, kStSample, true);
   mark(ctx, kStEstimate, false);
   s = smp_estimate(ctx, &q, At, same ? At : Bt, na2, same ? na2 : nb2, &om);

@@ -25,15 +25,30 @@ namespace {
 
 constexpr double kTwo32 = 4294967296.0;
 
-__global__ void block_sums_kernel(const float *__restrict__ x, int64_t n, double *__restrict__ out) {
+// out[b] = x[256 b] + x[256 b + 1] + ... in index order (binary64, no
+// contraction). One workgroup per block of 256 indices: the block is staged in
+// LDS with one load per thread, then summed by one thread.
+__global__ __launch_bounds__(256) void block_sums_kernel(const float *__restrict__ x, int64_t n,
+                                                         double *__restrict__ out) {
 #pragma clang fp contract(off)
+  __shared__ float v[256];
   const int64_t nb = (n + 255) / 256;
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    const int64_t e = std::min<int64_t>(n, (b + 1) * 256);
-    for (int64_t i = b * 256; i < e; ++i) s = s + (double)x[i];
-    out[b] = s;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int64_t i = b * 256 + threadIdx.x;
+    v[threadIdx.x] = i < n ? x[i] : 0.0f;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int cnt = (int)std::min<int64_t>(256, n - b * 256);
+      double s = 0.0;
+      for (int u = 0; u < cnt; ++u) s = s + (double)v[u];
+      out[b] = s;
+    }
+    __syncthreads();
   }
+}
+
+inline unsigned block_sums_grid(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
 }
 
 __global__ void totals_kernel(const double *__restrict__ ba, int64_t nba, const double *__restrict__ bb,
@@ -130,16 +145,14 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int64_t *__restrict__ 
   for (int64_t i = b; i < e; ++i) s += cnt[i];
   part[t] = s;
   __syncthreads();
-  if (t == 0) {
-    int64_t run = 0;
-    for (int u = 0; u < 1024; ++u) {
-      const int64_t v = part[u];
-      part[u] = run;
-      run += v;
-    }
+  // inclusive scan of the 1024 partial counts (Hillis-Steele)
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t add = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
   }
-  __syncthreads();
-  int64_t run = part[t];
+  int64_t run = part[t] - s;
   for (int64_t i = b; i < e; ++i) {
     ptr[i] = run;
     run += cnt[i];
@@ -243,8 +256,8 @@ inline unsigned grid_for(int64_t items, int per_block) {
 hipError_t sample_prepare(const float *na2, const float *nb2, int64_t n1, int64_t n2, SampleWs &ws,
                           hipStream_t st) {
   const int64_t nba = (n1 + 255) / 256, nbb = (n2 + 255) / 256;
-  hipLaunchKernelGGL(block_sums_kernel, dim3(grid_for(nba, 256)), dim3(256), 0, st, na2, n1, ws.blocks);
-  hipLaunchKernelGGL(block_sums_kernel, dim3(grid_for(nbb, 256)), dim3(256), 0, st, nb2, n2, ws.blocks + nba);
+  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n1)), dim3(256), 0, st, na2, n1, ws.blocks);
+  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n2)), dim3(256), 0, st, nb2, n2, ws.blocks + nba);
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, st, ws.blocks, nba, ws.blocks + nba, nbb, n1, n2,
                      ws.stats);
   hipLaunchKernelGGL(marginals_kernel, dim3(grid_for(n1 + n2, 256)), dim3(256), 0, st, na2, nb2, n1, n2, ws.stats,
@@ -276,7 +289,7 @@ hipError_t sample_fill(const SampleWs &ws, int64_t n1, int64_t n2, double m, uin
 // the block sums) into out[0]; out must hold 4 doubles.
 hipError_t fixed_total(const float *x, int64_t n, double *blocks, double *out, hipStream_t st) {
   const int64_t nb = (n + 255) / 256;
-  hipLaunchKernelGGL(block_sums_kernel, dim3(grid_for(nb, 256)), dim3(256), 0, st, x, n, blocks);
+  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n)), dim3(256), 0, st, x, n, blocks);
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, st, blocks, nb, blocks, (int64_t)0, n, n, out);
   return hipGetLastError();
 }
