@@ -113,37 +113,69 @@ __device__ __forceinline__ int64_t lower_bound_idx(const int32_t *__restrict__ a
   return lo;
 }
 
-__global__ __launch_bounds__(256) void estimate_tiles_kernel(
+// One 64 x 64 block of A~^T B~ per workgroup, then the estimates of the
+// block's sampled entries.
+//  * Products: 32-wide chunks of the sketch rows staged in LDS (FP32), four
+//    waves each owning a 32 x 32 quadrant on v_mfma_f64_16x16x4f64; every
+//    thread loads its share of chunk c + 1 into registers (clamped,
+//    unconditional loads, masked afterwards) while chunk c is multiplied.
+//  * The staging tiles and the FP64 dot block share one LDS buffer (33 KB),
+//    so four workgroups fit on a CU.
+//  * Epilogue: threads 0..63 find the entries of rows i0.. (CSR) and threads
+//    64..127 those of columns j0.. (CSC) whose other index falls in the block
+//    (binary search in the sorted listings) and cache the rows' and columns'
+//    norms in LDS; after a prefix sum over the 64 + 64 counts the block's
+//    entries are spread over all 256 threads, four in flight per thread.
+__global__ __launch_bounds__(256, 4) void estimate_tiles_kernel(
     const float *__restrict__ At, const float *__restrict__ Bt, int64_t n1, int64_t n2, int k,
     const double *__restrict__ na, const double *__restrict__ nb, const double *__restrict__ sa,
     const double *__restrict__ sb, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const int64_t *__restrict__ cp, const int32_t *__restrict__ ri, double *__restrict__ mt_csr,
     double *__restrict__ mt_csc) {
-  __shared__ float sA[kTS][kKCH + 1];
-  __shared__ float sB[kTS][kKCH + 1];
-  __shared__ double dot[kTS][kTS + 1];
+  constexpr int LD = kKCH + 1;
+  __shared__ double smem[kTS * (kTS + 1)];
+  __shared__ double r_s[kTS], r_n[kTS], c_s[kTS], c_n[kTS];
+  __shared__ int64_t lo_r[kTS], lo_c[kTS];
+  __shared__ int pre_r[kTS + 1], pre_c[kTS + 1];
+  float *sA = reinterpret_cast<float *>(smem);
+  float *sB = sA + kTS * LD;
+  double (*dot)[kTS + 1] = reinterpret_cast<double (*)[kTS + 1]>(smem);
   const int64_t i0 = (int64_t)blockIdx.y * kTS, j0 = (int64_t)blockIdx.x * kTS;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int wm = wave >> 1, wn = wave & 1;   // 32 x 32 quadrant of the block
   const int m = lane & 15, kk = lane >> 4;
+  // this thread's staging elements: rows (t >> 5) + 8 u, sketch row c0 + (t & 31)
+  const int cc = t & 31, rr0 = t >> 5;
   v4d acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  float pa[8], pb[8];
+  auto fetch = [&](int c0) {
+    const int c = c0 + cc < k ? c0 + cc : k - 1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + rr0 + 8 * u, j = j0 + rr0 + 8 * u;
+      pa[u] = At[(i < n1 ? i : n1 - 1) * k + c];
+      pb[u] = Bt[(j < n2 ? j : n2 - 1) * k + c];
+    }
+  };
+  fetch(0);
   for (int c0 = 0; c0 < k; c0 += kKCH) {
-    for (int e = t; e < kTS * kKCH; e += 256) {
-      const int rr = e / kKCH, cc = e % kKCH;
-      const int c = c0 + cc;
-      const int64_t i = i0 + rr, j = j0 + rr;
-      sA[rr][cc] = (i < n1 && c < k) ? At[i * k + c] : 0.0f;
-      sB[rr][cc] = (j < n2 && c < k) ? Bt[j * k + c] : 0.0f;
+    const bool cok = c0 + cc < k;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int rr = rr0 + 8 * u;
+      sA[rr * LD + cc] = (cok && i0 + rr < n1) ? pa[u] : 0.0f;
+      sB[rr * LD + cc] = (cok && j0 + rr < n2) ? pb[u] : 0.0f;
     }
     __syncthreads();
+    if (c0 + kKCH < k) fetch(c0 + kKCH);
 #pragma unroll
     for (int ks = 0; ks < kKCH; ks += 4) {
-      const double a0 = sA[wm * 32 + m][ks + kk], a1 = sA[wm * 32 + 16 + m][ks + kk];
-      const double b0 = sB[wn * 32 + m][ks + kk], b1 = sB[wn * 32 + 16 + m][ks + kk];
+      const double a0 = sA[(wm * 32 + m) * LD + ks + kk], a1 = sA[(wm * 32 + 16 + m) * LD + ks + kk];
+      const double b0 = sB[(wn * 32 + m) * LD + ks + kk], b1 = sB[(wn * 32 + 16 + m) * LD + ks + kk];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -158,23 +190,91 @@ __global__ __launch_bounds__(256) void estimate_tiles_kernel(
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) dot[wm * 32 + 16 * a + 4 * jj + kk][wn * 32 + 16 * b + m] = acc[a][b][jj];
-  __syncthreads();
   if (t < kTS) {
     const int64_t i = i0 + t;
+    int64_t lo = 0, cnt = 0;
+    double s_ = 0.0, n_ = 0.0;
     if (i < n1) {
       const int64_t end = rp[i + 1];
-      for (int64_t e = lower_bound_idx(ci, rp[i], end, j0); e < end && ci[e] < j0 + kTS; ++e) {
-        const int64_t j = ci[e];
-        mt_csr[e] = rescaled(sa[i], sb[j], na[i], nb[j], dot[t][j - j0]);
-      }
+      lo = lower_bound_idx(ci, rp[i], end, j0);
+      cnt = lower_bound_idx(ci, lo, end, j0 + kTS) - lo;
+      s_ = sa[i];
+      n_ = na[i];
     }
+    lo_r[t] = lo;
+    pre_r[t + 1] = (int)cnt;
+    r_s[t] = s_;
+    r_n[t] = n_;
   } else if (t < 2 * kTS) {
-    const int64_t j = j0 + (t - kTS);
+    const int u = t - kTS;
+    const int64_t j = j0 + u;
+    int64_t lo = 0, cnt = 0;
+    double s_ = 0.0, n_ = 0.0;
     if (j < n2) {
       const int64_t end = cp[j + 1];
-      for (int64_t e = lower_bound_idx(ri, cp[j], end, i0); e < end && ri[e] < i0 + kTS; ++e) {
-        const int64_t i = ri[e];
-        mt_csc[e] = rescaled(sa[i], sb[j], na[i], nb[j], dot[i - i0][t - kTS]);
+      lo = lower_bound_idx(ri, cp[j], end, i0);
+      cnt = lower_bound_idx(ri, lo, end, i0 + kTS) - lo;
+      s_ = sb[j];
+      n_ = nb[j];
+    }
+    lo_c[u] = lo;
+    pre_c[u + 1] = (int)cnt;
+    c_s[u] = s_;
+    c_n[u] = n_;
+  }
+  __syncthreads();
+  if (t == 0) {
+    pre_r[0] = 0;
+    for (int u = 0; u < kTS; ++u) pre_r[u + 1] += pre_r[u];
+  } else if (t == 64) {
+    pre_c[0] = 0;
+    for (int u = 0; u < kTS; ++u) pre_c[u + 1] += pre_c[u];
+  }
+  __syncthreads();
+  // entry f of the block's listing: owner r = the last with pre[r] <= f
+  auto owner = [](const int *pre, int f) {
+    int lo = 0, hi = kTS;   // pre[lo] <= f < pre[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] <= f) lo = mid;
+      else hi = mid;
+    }
+    return lo;
+  };
+  const int tot_r = pre_r[kTS], tot_c = pre_c[kTS];
+  for (int f0 = 0; f0 < tot_r; f0 += 4 * 256) {
+    int64_t e[4];
+    int r[4], jj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = min(f0 + q * 256 + t, tot_r - 1);
+      r[q] = owner(pre_r, f);
+      e[q] = lo_r[r[q]] + (f - pre_r[r[q]]);
+      jj[q] = ci[e[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (f0 + q * 256 + t < tot_r) {
+        const int cj = (int)(jj[q] - j0);
+        mt_csr[e[q]] = rescaled(r_s[r[q]], c_s[cj], r_n[r[q]], c_n[cj], dot[r[q]][cj]);
+      }
+    }
+  }
+  for (int f0 = 0; f0 < tot_c; f0 += 4 * 256) {
+    int64_t e[4];
+    int c[4], ii[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = min(f0 + q * 256 + t, tot_c - 1);
+      c[q] = owner(pre_c, f);
+      e[q] = lo_c[c[q]] + (f - pre_c[c[q]]);
+      ii[q] = ri[e[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (f0 + q * 256 + t < tot_c) {
+        const int ri_ = (int)(ii[q] - i0);
+        mt_csc[e[q]] = rescaled(r_s[ri_], c_s[c[q]], r_n[ri_], c_n[c[q]], dot[ri_][c[q]]);
       }
     }
   }
