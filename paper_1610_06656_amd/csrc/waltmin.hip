@@ -50,6 +50,14 @@ constexpr int kInitOversample = 10;
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)std::max<int64_t>(1, (a + b - 1) / b); }
 
+// Lane `src`'s value of v, in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------- Gram
 // part[b][a*p + c] = sum over the rows of block b of X[i][a] X[i][c], on the
 // FP64 matrix cores: wave w of the block takes the row quads w, w + 4, ...
@@ -146,6 +154,11 @@ __global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, in
 // (right-looking; a pivot <= 1e-13 of the largest diagonal entry drops that
 // direction), inverts L by forward substitution (one column per thread) and
 // writes M = L^-T, so that X M has orthonormal columns when X^T X = G.
+// With D > 0 (p <= D <= 32) the factorisation and the inverse run on one wave
+// in registers: lane i holds row i of G (then of L), pivots and entries are
+// broadcast with v_readlane, the same operations in the same order; lane t
+// then computes column t of L^-1 and writes row t of M.
+template <int D>
 __global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict__ part, int nblk, int p,
                                                        double shift_rel, double *__restrict__ M) {
   __shared__ double L[kMaxP * kMaxP];
@@ -155,6 +168,50 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict_
   const int pp = p * p;
   for (int idx = t; idx < pp; idx += 256) L[idx] = sum_partials(part, nblk, pp, idx);
   __syncthreads();
+  if constexpr (D > 0) {
+    if (t >= 64) return;
+    double tr = 0.0, mx = 0.0;
+    for (int a = 0; a < p; ++a) {
+      tr += L[a * p + a];
+      mx = fmax(mx, L[a * p + a]);
+    }
+    const double shift = shift_rel > 0.0 ? shift_rel * tr / p : 0.0;
+    const double tol = 1e-13 * (mx + shift);
+    double l[D], dv[D], y[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) l[k] = (t < p && k < p) ? L[t * p + k] + (k == t ? shift : 0.0) : 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      dv[j] = 0.0;
+      if (j < p) {
+        const double piv = readlane_f64(l[j], j);
+        const bool ok = piv > tol && mx > 0.0;
+        const double d = ok ? sqrt(piv) : 0.0;
+        dv[j] = ok ? 1.0 / d : 0.0;
+        l[j] = t == j ? d : (t > j ? (ok ? l[j] / d : 0.0) : l[j]);
+#pragma unroll
+        for (int k = j + 1; k < D; ++k)
+          if (k < p) l[k] -= l[j] * readlane_f64(l[j], k);   // only k <= t is kept in lane t
+      }
+    }
+    // y = column t of L^-1 (entries above t stay 0)
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      y[i] = 0.0;
+      if (i < p) {
+        double sum = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) sum -= readlane_f64(l[k], i) * y[k];
+        y[i] = sum * dv[i];
+      }
+    }
+    if (t < p) {
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        if (a < p) M[t * p + a] = y[a];
+    }
+    return;
+  }
   double tr = 0.0, mx = 0.0;
   for (int a = 0; a < p; ++a) {
     tr += L[a * p + a];
@@ -229,7 +286,26 @@ __global__ void apply_kernel(const double *X, int64_t n, int pin, const double *
 // entries that only the small diagonal entries would have to outgrow.
 __device__ __forceinline__ bool jacobi_negligible(double apq, double app, double aqq, double dmax) {
   const double a = fabs(apq);
-  return a <= 1e-15 * sqrt(fabs(app * aqq)) || a <= 1e-17 * dmax;
+  return a * a <= 1e-30 * fabs(app * aqq) || a <= 1e-17 * dmax;   // squared: no sqrt on the rotation's path
+}
+
+// Pair k of round rd of the round-robin schedule over m + 1 players (m odd):
+// (m, rd) and (rd + k, rd - k) mod m, lower index first.
+__device__ __forceinline__ void jacobi_pair(int rd, int k, int m, int &P, int &Q) {
+  if (k == 0) {
+    P = m;
+    Q = rd;
+  } else {
+    P = rd + k;
+    if (P >= m) P -= m;
+    Q = rd - k;
+    if (Q < 0) Q += m;
+  }
+  if (P > Q) {
+    const int tmp = P;
+    P = Q;
+    Q = tmp;
+  }
 }
 
 template <int NT>
@@ -238,7 +314,6 @@ __global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict
   __shared__ double A[kMaxP * kMaxP];
   __shared__ double V[kMaxP * kMaxP];
   __shared__ double cs[kMaxP / 2][2];
-  __shared__ int pr[kMaxP / 2][2];
   __shared__ double red[64];
   __shared__ int any_left;
   const int t = threadIdx.x;
@@ -248,7 +323,16 @@ __global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict
   }
   __syncthreads();
   const int pe = (p + 1) & ~1;   // even number of players; index p is a dummy when p is odd
-  const int half = pe / 2;
+  const int half = pe / 2, m = pe - 1;
+  // this thread's (pair, index) tasks of the update phases; half * p <= 2 NT
+  // for the sizes each NT is launched for
+  int upi[2], ui[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = t + u * NT;
+    upi[u] = e < half * p ? e / p : -1;
+    ui[u] = e < half * p ? e % p : 0;
+  }
   for (int sweep = 0; sweep < 40 && p > 1; ++sweep) {
     double dmax = 0.0;
     for (int a = 0; a < p; ++a) dmax = fmax(dmax, fabs(A[a * p + a]));
@@ -260,57 +344,56 @@ __global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict
     }
     __syncthreads();
     if (any_left == 0) break;
-    for (int rd = 0; rd < pe - 1; ++rd) {
+    for (int rd = 0; rd < m; ++rd) {
       if (t < half) {
         int P, Q;
-        if (t == 0) {
-          P = pe - 1;
-          Q = rd;
-        } else {
-          P = (rd + t) % (pe - 1);
-          Q = (rd - t + (pe - 1)) % (pe - 1);
-        }
-        if (P > Q) { const int tmp = P; P = Q; Q = tmp; }
+        jacobi_pair(rd, t, m, P, Q);
         double c = 1.0, s = 0.0;
         if (Q < p) {
-          const double apq = A[P * p + Q];
-          if (!jacobi_negligible(apq, A[P * p + P], A[Q * p + Q], dmax)) {
-            const double tau = (A[Q * p + Q] - A[P * p + P]) / (2.0 * apq);
+          const double apq = A[P * p + Q], app = A[P * p + P], aqq = A[Q * p + Q];
+          if (!jacobi_negligible(apq, app, aqq, dmax)) {
+            const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
           }
         }
-        pr[t][0] = P;
-        pr[t][1] = Q;
         cs[t][0] = c;
         cs[t][1] = s;
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int e = t; e < half * p; e += NT) {
-        const int pi = e / p, i = e % p;
-        const int P = pr[pi][0], Q = pr[pi][1];
-        if (Q < p) {
-          const double c = cs[pi][0], s = cs[pi][1];
-          const double aip = A[i * p + P], aiq = A[i * p + Q];
-          A[i * p + P] = c * aip - s * aiq;
-          A[i * p + Q] = s * aip + c * aiq;
-          const double vip = V[i * p + P], viq = V[i * p + Q];
-          V[i * p + P] = c * vip - s * viq;
-          V[i * p + Q] = s * vip + c * viq;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int pi = upi[u], i = ui[u];
+        if (pi >= 0) {
+          int P, Q;
+          jacobi_pair(rd, pi, m, P, Q);
+          if (Q < p) {
+            const double c = cs[pi][0], s = cs[pi][1];
+            const double aip = A[i * p + P], aiq = A[i * p + Q];
+            A[i * p + P] = c * aip - s * aiq;
+            A[i * p + Q] = s * aip + c * aiq;
+            const double vip = V[i * p + P], viq = V[i * p + Q];
+            V[i * p + P] = c * vip - s * viq;
+            V[i * p + Q] = s * vip + c * viq;
+          }
         }
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int e = t; e < half * p; e += NT) {
-        const int pi = e / p, j = e % p;
-        const int P = pr[pi][0], Q = pr[pi][1];
-        if (Q < p) {
-          const double c = cs[pi][0], s = cs[pi][1];
-          const double apj = A[P * p + j], aqj = A[Q * p + j];
-          A[P * p + j] = c * apj - s * aqj;
-          A[Q * p + j] = s * apj + c * aqj;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int pi = upi[u], j = ui[u];
+        if (pi >= 0) {
+          int P, Q;
+          jacobi_pair(rd, pi, m, P, Q);
+          if (Q < p) {
+            const double c = cs[pi][0], s = cs[pi][1];
+            const double apj = A[P * p + j], aqj = A[Q * p + j];
+            A[P * p + j] = c * apj - s * aqj;
+            A[Q * p + j] = s * apj + c * aqj;
+          }
         }
       }
       __syncthreads();
@@ -501,14 +584,6 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, i
 }
 
 // ---------------------------------------------------------------- weighted LS solves
-// Lane `src`'s value of v, in every lane.
-__device__ __forceinline__ double readlane_f64(double v, int src) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
 // One workgroup (4 waves) per output row o; RT = ceil((r+1)/16) MFMA tiles per
 // side. Each wave takes every fourth chunk of 64 entries: the chunk's metadata
 // is loaded one entry per lane, then BATCH groups of four entries have their
@@ -831,7 +906,12 @@ void apply(const double *X, int64_t n, int pin, const double *M, int pout, doubl
 // span preserved; twice gives orthonormal columns to working precision.
 void cholqr_pass(const Ws &w, const double *X, int64_t n, int p, double shift_rel, double *Xout, hipStream_t st) {
   const int nblk = gram(w, X, n, p, st);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
+  if (p <= 16)
+    hipLaunchKernelGGL(chol_inv_kernel<16>, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
+  else if (p <= 32)
+    hipLaunchKernelGGL(chol_inv_kernel<32>, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
+  else
+    hipLaunchKernelGGL(chol_inv_kernel<0>, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
   apply(X, n, p, w.M, p, Xout, st);
 }
 
