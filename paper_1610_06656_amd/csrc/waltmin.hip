@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict_
         const bool ok = piv > tol && mx > 0.0;
         const double d = ok ? sqrt(piv) : 0.0;
         dv[j] = ok ? 1.0 / d : 0.0;
-        l[j] = t == j ? d : (t > j ? (ok ? l[j] / d : 0.0) : l[j]);
+        l[j] = t == j ? d : (t > j ? l[j] * dv[j] : l[j]);
 #pragma unroll
         for (int k = j + 1; k < D; ++k)
           if (k < p) l[k] -= l[j] * readlane_f64(l[j], k);   // only k <= t is kept in lane t
@@ -718,8 +718,9 @@ __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restr
   if constexpr (RT == 1) {
     // r <= 15: the same steps with row i of the system in the registers of
     // lane i (pivots and solution entries broadcast with v_readlane); the
-    // back substitution reads the columns of L through LDS once.
-    double l[D], Lc[D];
+    // back substitution reads the columns of L through LDS once. Each pivot's
+    // reciprocal is taken once and multiplied (one division per column).
+    double l[D], Lc[D], dv[D];
     bool solved = false;
     double x = 0.0;
     for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
@@ -731,13 +732,15 @@ __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restr
       bool ok = true;
 #pragma unroll
       for (int j = 0; j < D; ++j) {
+        dv[j] = 0.0;
         if (j < r && ok) {
           const double piv = readlane_f64(l[j], j);
           if (!(piv > tol)) {
             ok = false;
           } else {
             const double d = sqrt(piv);
-            l[j] = t == j ? d : (t > j ? l[j] / d : l[j]);
+            dv[j] = 1.0 / d;
+            l[j] = t == j ? d : (t > j ? l[j] * dv[j] : l[j]);
 #pragma unroll
             for (int k = j + 1; k < D; ++k)
               if (k < r) l[k] -= l[j] * readlane_f64(l[j], k);   // only k <= t is kept in lane t
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restr
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         if (k < r) {
-          const double yk = readlane_f64(y, k) / readlane_f64(l[k], k);
+          const double yk = readlane_f64(y, k) * dv[k];
           y = t == k ? yk : (t > k ? y - l[k] * yk : y);
         }
       }
@@ -763,7 +766,7 @@ __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restr
 #pragma unroll
       for (int k = D - 1; k >= 0; --k) {
         if (k < r) {
-          const double xk = readlane_f64(y, k) / readlane_f64(l[k], k);
+          const double xk = readlane_f64(y, k) * dv[k];
           y = t == k ? xk : (t < k ? y - Lc[k] * xk : y);
         }
       }
