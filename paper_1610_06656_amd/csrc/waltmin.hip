@@ -2,7 +2,7 @@
 //
 // Init (Alg. 2 steps 4-6): the top-r singular subspace of R = w .* P_Omega0(M~)
 // by block subspace iteration (Halko, Martinsson, Tropp 2011, Alg. 4.4) on a
-// block of p = r + 10 columns: Y <- orth(R^T orth(R Y)), then a Rayleigh-Ritz
+// block of p = r + 5 columns: Y <- orth(R^T orth(R Y)), then a Rayleigh-Ritz
 // step on R Y gives U0, S0, V0; rows of U0 with ||U0_i|| > 8 sqrt(r) ||A_i||/||A||_F
 // are zeroed (the trim of step 6, with the row-norm bound the paper states
 // for the trimmed initial iterate in the proof of its initialisation lemma).
@@ -46,7 +46,7 @@ hipError_t fixed_total(const float *x, int64_t n, double *blocks, double *out, h
 namespace {
 
 constexpr int kMaxP = 64;       // largest block width handled by the small kernels
-constexpr int kInitOversample = 10;
+constexpr int kInitOversample = 5;
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)std::max<int64_t>(1, (a + b - 1) / b); }
 

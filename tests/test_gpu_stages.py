@@ -264,7 +264,7 @@ WALTMIN_CASES = {
     "ragged_r3": dict(d=1200, n1=77, n2=131, k=60, r=3, T=6),
     "r20_tiles": dict(d=3000, n=160, k=200, r=20, T=5, R=20),
     "split": dict(d=2000, n=200, k=100, r=4, T=2, split=True, mscale=6.0),
-    "r24_wide": dict(d=3000, n=220, k=240, r=24, T=4, R=24),   # p = 34 columns in the initial subspace
+    "r28_wide": dict(d=3000, n=220, k=240, r=28, T=4, R=28),   # p = 33 columns in the initial subspace
 }
 
 
