@@ -591,12 +591,14 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, i
 // at once when RT = 1); the wave's next chunk's metadata is requested right
 // after the first batch of rows, so that the two loads overlap. The four waves'
 // Gram tiles are summed in LDS and the r x r system is solved there.
-template <int RT>
+// R > 0: the instantiation for r = R (RT = 1 only); R = 0: any r of the tile width.
+template <int RT, int R>
 __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                        const double *__restrict__ w, const double *__restrict__ mt,
                                                        const uint8_t *__restrict__ sub, int sel,
                                                        const double *__restrict__ Q, int r, int64_t n_out,
                                                        double *__restrict__ Xout) {
+  static_assert(RT != 1 || R > 0, "the one-tile kernel is instantiated per r");
   constexpr int D = RT * 16;
   constexpr int BATCH = RT == 1 ? 16 : (RT == 2 ? 8 : 4);
   __shared__ double Gw[4 * D * D];
@@ -719,21 +721,24 @@ __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restr
     // r <= 15: the same steps with row i of the system in the registers of
     // lane i (pivots and solution entries broadcast with v_readlane); the
     // back substitution reads the columns of L through LDS once. Each pivot's
-    // reciprocal is taken once and multiplied (one division per column).
-    double l[D], Lc[D], dv[D];
+    // reciprocal is taken once and multiplied (one division per column). The
+    // kernel is instantiated for each r (R = r), so every bound below is a
+    // compile-time constant and the unrolled loops carry no guards.
+    constexpr int RR = R > 0 ? R : D;
+    double l[RR], Lc[RR], dv[RR];
     bool solved = false;
     double x = 0.0;
     for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
       const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
       const double tol = 1e-12 * (mx + shift);
 #pragma unroll
-      for (int k = 0; k < D; ++k) l[k] = (t < r && k < r) ? G[t * D + k] + (k == t ? shift : 0.0) : 0.0;
-      double y = t < r ? G[t * D + r] : 0.0;
+      for (int k = 0; k < RR; ++k) l[k] = (t < RR && k < r) ? G[t * D + k] + (k == t ? shift : 0.0) : 0.0;
+      double y = t < RR ? G[t * D + r] : 0.0;
       bool ok = true;
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
+      for (int j = 0; j < RR; ++j) {
         dv[j] = 0.0;
-        if (j < r && ok) {
+        if (ok) {
           const double piv = readlane_f64(l[j], j);
           if (!(piv > tol)) {
             ok = false;
@@ -742,33 +747,28 @@ __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restr
             dv[j] = 1.0 / d;
             l[j] = t == j ? d : (t > j ? l[j] * dv[j] : l[j]);
 #pragma unroll
-            for (int k = j + 1; k < D; ++k)
-              if (k < r) l[k] -= l[j] * readlane_f64(l[j], k);   // only k <= t is kept in lane t
+            for (int k = j + 1; k < RR; ++k) l[k] -= l[j] * readlane_f64(l[j], k);   // only k <= t is kept in lane t
           }
         }
       }
       if (!ok) continue;
       // forward: L y = h
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        if (k < r) {
-          const double yk = readlane_f64(y, k) * dv[k];
-          y = t == k ? yk : (t > k ? y - l[k] * yk : y);
-        }
+      for (int k = 0; k < RR; ++k) {
+        const double yk = readlane_f64(y, k) * dv[k];
+        y = t == k ? yk : (t > k ? y - l[k] * yk : y);
       }
       // backward: L^T x = y; lane t needs column t of L
 #pragma unroll
-      for (int k = 0; k < D; ++k)
-        if (t < r && k <= t) L[t * 32 + k] = l[k];
+      for (int k = 0; k < RR; ++k)
+        if (t < RR && k <= t) L[t * 32 + k] = l[k];
       wsync();
 #pragma unroll
-      for (int k = 0; k < D; ++k) Lc[k] = (k < r && k > t) ? L[k * 32 + t] : 0.0;
+      for (int k = 0; k < RR; ++k) Lc[k] = k > t ? L[k * 32 + t] : 0.0;
 #pragma unroll
-      for (int k = D - 1; k >= 0; --k) {
-        if (k < r) {
-          const double xk = readlane_f64(y, k) * dv[k];
-          y = t == k ? xk : (t < k ? y - Lc[k] * xk : y);
-        }
+      for (int k = RR - 1; k >= 0; --k) {
+        const double xk = readlane_f64(y, k) * dv[k];
+        y = t == k ? xk : (t < k ? y - Lc[k] * xk : y);
       }
       x = y;
       solved = true;
@@ -941,16 +941,30 @@ void spmm(const int64_t *ptr, const int32_t *idx, const double *wt, const double
     hipLaunchKernelGGL(spmm_kernel<64>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Xout);
 }
 
+template <int R>
+void ls_solve_r(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub,
+                int sel, const double *Q, int64_t n_out, double *Xout, hipStream_t st) {
+  hipLaunchKernelGGL((ls_solve_kernel<1, R>), dim3((unsigned)std::max<int64_t>(1, n_out)), dim3(256), 0, st, ptr, idx,
+                     wt, mt, sub, sel, Q, R, n_out, Xout);
+}
+
+typedef void (*LsLaunch)(const int64_t *, const int32_t *, const double *, const double *, const uint8_t *, int,
+                         const double *, int64_t, double *, hipStream_t);
+const LsLaunch kLsByR[16] = {nullptr,       ls_solve_r<1>,  ls_solve_r<2>,  ls_solve_r<3>,  ls_solve_r<4>,
+                             ls_solve_r<5>,  ls_solve_r<6>,  ls_solve_r<7>,  ls_solve_r<8>,  ls_solve_r<9>,
+                             ls_solve_r<10>, ls_solve_r<11>, ls_solve_r<12>, ls_solve_r<13>, ls_solve_r<14>,
+                             ls_solve_r<15>};
+
 void ls_solve(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
               const double *Q, int r, int64_t n_out, double *Xout, hipStream_t st) {
   const int rt = (r + 1 + 15) / 16;
   const dim3 grid((unsigned)std::max<int64_t>(1, n_out));
   if (rt == 1)
-    hipLaunchKernelGGL(ls_solve_kernel<1>, grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    kLsByR[r](ptr, idx, wt, mt, sub, sel, Q, n_out, Xout, st);
   else if (rt == 2)
-    hipLaunchKernelGGL(ls_solve_kernel<2>, grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    hipLaunchKernelGGL((ls_solve_kernel<2, 0>), grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
   else
-    hipLaunchKernelGGL(ls_solve_kernel<3>, grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    hipLaunchKernelGGL((ls_solve_kernel<3, 0>), grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
 }
 
 // U (n1 x r), V (n2 x r, orthonormal columns) -> canonical Uc, sigma, Vc
