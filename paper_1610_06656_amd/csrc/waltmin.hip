@@ -420,7 +420,7 @@ __global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict
 // The rounds are latency-bound chains (rotation, then the column and row
 // updates); more threads shorten the update phases of the larger problems.
 void jacobi_eig(const double *G, int p, double *W, double *lam, hipStream_t st) {
-  if (p <= 16)
+  if (p <= 10)
     hipLaunchKernelGGL(jacobi_eig_kernel<64>, dim3(1), dim3(64), 0, st, G, p, W, lam);
   else if (p <= 32)
     hipLaunchKernelGGL(jacobi_eig_kernel<256>, dim3(1), dim3(256), 0, st, G, p, W, lam);
