@@ -142,12 +142,6 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return sum;
 }
 
-__global__ void gram_reduce_kernel(const double *__restrict__ part, int nblk, int p, double *__restrict__ G) {
-  const int pp = p * p;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < pp; idx += gridDim.x * blockDim.x)
-    G[idx] = sum_partials(part, nblk, pp, idx);
-}
-
 // ---------------------------------------------------------------- Cholesky -> L^-T
 // One workgroup: sums the nblk Gram partials (fixed order) into G, adds
 // shift_rel * trace/p to the diagonal when shift_rel > 0, factors G = L L^T
@@ -257,6 +251,37 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict_
   }
 }
 
+// Two products in one launch: Xo1 = X1 M1 (n1 rows; blocks 0 .. nb1-1) and
+// Xo2 = X2 M2 (n2 rows), each n x pin times pin x pout, one wave per row. When
+// na2 is given, rows of Xo1 whose norm exceeds 8 sqrt(pout) sqrt(na2_i / FA)
+// are set to zero (the trim of Alg. 2 step 6; the squared norm is summed in
+// column order).
+__global__ void apply2_kernel(const double *__restrict__ X1, int64_t n1, const double *__restrict__ M1,
+                              double *__restrict__ Xo1, const float *__restrict__ na2, const double *__restrict__ FA,
+                              const double *__restrict__ X2, int64_t n2, const double *__restrict__ M2,
+                              double *__restrict__ Xo2, int pin, int pout, int64_t nb1) {
+  const int lane = threadIdx.x & 63;
+  const bool first = blockIdx.x < nb1;
+  const int64_t i = (first ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - nb1) * 4 + (threadIdx.x >> 6);
+  if (i >= (first ? n1 : n2)) return;
+  const double *row = (first ? X1 : X2) + i * pin;
+  const double *M = first ? M1 : M2;
+  double s = 0.0;
+  if (lane < pout)
+    for (int b = 0; b < pin; ++b) s = fma(row[b], M[b * pout + lane], s);
+  if (first && na2) {
+    double ss = 0.0;
+    for (int a = 0; a < pout; ++a) {
+      const double v = readlane_f64(s, a);
+      ss += v * v;
+    }
+    const double fa = FA[0];
+    const double thr = fa > 0.0 ? 8.0 * sqrt((double)pout) * sqrt((double)na2[i] / fa) : 0.0;
+    if (sqrt(ss) > thr) s = 0.0;
+  }
+  if (lane < pout) (first ? Xo1 : Xo2)[i * pout + lane] = s;
+}
+
 // Xout (n x pout) = X (n x pin) * M (pin x pout), row-major. One wave per row,
 // lane a computes output column a; every lane reads the whole input row before
 // any lane writes, so Xout may alias X when pin == pout.
@@ -274,9 +299,11 @@ __global__ void apply_kernel(const double *X, int64_t n, int pin, const double *
 }
 
 // ---------------------------------------------------------------- Jacobi eigen
-// Symmetric G (p x p) -> eigenvalues (descending) lam[p], eigenvectors W (p x p,
-// column c is the c-th eigenvector). One workgroup; cyclic Jacobi with the
-// round-robin pairing so the p/2 rotations of a round are disjoint.
+// G = the sum of the nblk Gram partials (p x p, symmetrised) -> its
+// eigenpairs, sorted by descending eigenvalue, and from the top r of them the
+// maps Mu, Mv (p x r) and sigma of the Rayleigh-Ritz and canonical steps.
+// One workgroup; cyclic Jacobi with the round-robin pairing so the p/2
+// rotations of a round are disjoint.
 // An off-diagonal entry is negligible when it is at most 1e-15 of the geometric
 // mean of its two diagonal entries or 1e-17 of the largest diagonal magnitude;
 // negligible entries are not rotated, and the iteration stops at the first
@@ -309,18 +336,22 @@ __device__ __forceinline__ void jacobi_pair(int rd, int k, int m, int &P, int &Q
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict__ G, int p, double *__restrict__ W,
-                                                        double *__restrict__ lam) {
+__global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict__ part, int nblk, int p, int r,
+                                                        double *__restrict__ Mu, double *__restrict__ Mv,
+                                                        double *__restrict__ sigma) {
   __shared__ double A[kMaxP * kMaxP];
   __shared__ double V[kMaxP * kMaxP];
   __shared__ double cs[kMaxP / 2][2];
+  __shared__ double lam[kMaxP];
   __shared__ double red[64];
   __shared__ int any_left;
   const int t = threadIdx.x;
-  for (int e = t; e < p * p; e += NT) {
-    A[e] = 0.5 * (G[e] + G[(e % p) * p + e / p]);
-    V[e] = (e / p == e % p) ? 1.0 : 0.0;
-  }
+  const int pp = p * p;
+  for (int e = t; e < pp; e += NT) V[e] = sum_partials(part, nblk, pp, e);   // G, summed in block order
+  __syncthreads();
+  for (int e = t; e < pp; e += NT) A[e] = 0.5 * (V[e] + V[(e % p) * p + e / p]);
+  __syncthreads();
+  for (int e = t; e < pp; e += NT) V[e] = (e / p == e % p) ? 1.0 : 0.0;
   __syncthreads();
   const int pe = (p + 1) & ~1;   // even number of players; index p is a dummy when p is odd
   const int half = pe / 2, m = pe - 1;
@@ -411,40 +442,33 @@ __global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict
     red[rank] = (double)t;
   }
   __syncthreads();
-  for (int e = t; e < p * p; e += NT) {
-    const int i = e / p, a = e % p;
-    W[e] = V[i * p + (int)red[a]];
+  // Rayleigh-Ritz / canonical maps of the top r pairs (eigenvector a is
+  // column red[a] of V): Mu = W_r diag(1/sqrt(lam)), Mv = W_r, sigma =
+  // sqrt(lam), with components of lam <= 1e-28 lam_max set to 0
+  const double lmax = lam[0];
+  for (int e = t; e < p * r; e += NT) {
+    const int b = e / r, a = e % r;
+    const double l = lam[a];
+    const bool ok = l > 1e-28 * lmax && l > 0.0;
+    const double wv = V[b * p + (int)red[a]];
+    Mu[e] = ok ? wv / sqrt(l) : 0.0;
+    Mv[e] = wv;
+  }
+  if (t < r) {
+    const double l = lam[t];
+    sigma[t] = (l > 1e-28 * lmax && l > 0.0) ? sqrt(l) : 0.0;
   }
 }
 
 // The rounds are latency-bound chains (rotation, then the column and row
 // updates); more threads shorten the update phases of the larger problems.
-void jacobi_eig(const double *G, int p, double *W, double *lam, hipStream_t st) {
+void jacobi_eig(const double *part, int nblk, int p, int r, double *Mu, double *Mv, double *sigma, hipStream_t st) {
   if (p <= 10)
-    hipLaunchKernelGGL(jacobi_eig_kernel<64>, dim3(1), dim3(64), 0, st, G, p, W, lam);
+    hipLaunchKernelGGL(jacobi_eig_kernel<64>, dim3(1), dim3(64), 0, st, part, nblk, p, r, Mu, Mv, sigma);
   else if (p <= 32)
-    hipLaunchKernelGGL(jacobi_eig_kernel<256>, dim3(1), dim3(256), 0, st, G, p, W, lam);
+    hipLaunchKernelGGL(jacobi_eig_kernel<256>, dim3(1), dim3(256), 0, st, part, nblk, p, r, Mu, Mv, sigma);
   else
-    hipLaunchKernelGGL(jacobi_eig_kernel<1024>, dim3(1), dim3(1024), 0, st, G, p, W, lam);
-}
-
-// From the eigenpairs of a Gram matrix, build the maps of a Rayleigh-Ritz /
-// canonical step for the top r pairs: Mu = W_r diag(1/sqrt(lam)), Mv = W_r,
-// sigma = sqrt(lam) (components with lam <= 1e-28 lam_max are set to 0).
-__global__ void ritz_maps_kernel(const double *__restrict__ W, const double *__restrict__ lam, int p, int r,
-                                 double *__restrict__ Mu, double *__restrict__ Mv, double *__restrict__ sigma) {
-  const double lmax = lam[0];
-  for (int e = threadIdx.x; e < p * r; e += blockDim.x) {
-    const int b = e / r, a = e % r;
-    const double l = lam[a];
-    const bool ok = l > 1e-28 * lmax && l > 0.0;
-    Mu[e] = ok ? W[b * p + a] / sqrt(l) : 0.0;
-    Mv[e] = W[b * p + a];
-  }
-  if (threadIdx.x < r) {
-    const double l = lam[threadIdx.x];
-    sigma[threadIdx.x] = (l > 1e-28 * lmax && l > 0.0) ? sqrt(l) : 0.0;
-  }
+    hipLaunchKernelGGL(jacobi_eig_kernel<1024>, dim3(1), dim3(1024), 0, st, part, nblk, p, r, Mu, Mv, sigma);
 }
 
 // ---------------------------------------------------------------- sparse products
@@ -532,20 +556,7 @@ __global__ void gaussian_block_kernel(int64_t n, int p, uint64_t seed, double *_
   }
 }
 
-// ---------------------------------------------------------------- trim, scale, sign
-__global__ void trim_kernel(double *__restrict__ U, int64_t n, int r, const float *__restrict__ na2,
-                            const double *__restrict__ FA) {
-  const double fa = FA[0];
-  const double c = 8.0 * sqrt((double)r);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int a = 0; a < r; ++a) s += U[i * r + a] * U[i * r + a];
-    const double thr = fa > 0.0 ? c * sqrt((double)na2[i] / fa) : 0.0;
-    if (sqrt(s) > thr)
-      for (int a = 0; a < r; ++a) U[i * r + a] = 0.0;
-  }
-}
-
+// ---------------------------------------------------------------- scale, sign
 __global__ void scale_cols_kernel(double *__restrict__ U, int64_t n, int r, const double *__restrict__ s) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * r; e += (int64_t)gridDim.x * blockDim.x)
     U[e] *= s[e % r];
@@ -832,9 +843,9 @@ __global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restr
 struct Ws {
   double *FA;       // [1]
   double *blocks;   // n1/256 + 1
-  double *X, *Y, *T1, *T2;  // n1*p, n2*p, max(n1,n2)*p (x2)
+  double *X, *Y;     // n1*p, n2*p
   double *part;     // gram partials
-  double *G, *M, *W, *lam, *Mu, *Mv, *sig;
+  double *M, *Mu, *Mv, *sig;
   double *U, *V;    // n1*r, n2*r iterates
 };
 
@@ -849,19 +860,13 @@ T *carve(char *&p, size_t count) {
 
 Ws carve_ws(void *base, int64_t n1, int64_t n2, int p, int r) {
   char *c = static_cast<char *>(base);
-  const int64_t nm = std::max(n1, n2);
   Ws w;
   w.FA = carve<double>(c, 4);
   w.blocks = carve<double>(c, n1 / 256 + 2);
   w.X = carve<double>(c, n1 * p);
   w.Y = carve<double>(c, n2 * p);
-  w.T1 = carve<double>(c, nm * p);
-  w.T2 = carve<double>(c, nm * p);
   w.part = carve<double>(c, (size_t)kGramBlocks * kMaxP * kMaxP);
-  w.G = carve<double>(c, kMaxP * kMaxP);
   w.M = carve<double>(c, kMaxP * kMaxP);
-  w.W = carve<double>(c, kMaxP * kMaxP);
-  w.lam = carve<double>(c, kMaxP);
   w.Mu = carve<double>(c, kMaxP * kMaxP);
   w.Mv = carve<double>(c, kMaxP * kMaxP);
   w.sig = carve<double>(c, kMaxP);
@@ -871,11 +876,10 @@ Ws carve_ws(void *base, int64_t n1, int64_t n2, int p, int r) {
 }
 
 size_t carve_bytes(int64_t n1, int64_t n2, int p, int r) {
-  const int64_t nm = std::max(n1, n2);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t s = 0;
-  s += al(4 * 8) + al((n1 / 256 + 2) * 8) + al(n1 * p * 8) + al(n2 * p * 8) + 2 * al(nm * p * 8);
-  s += al((size_t)kGramBlocks * kMaxP * kMaxP * 8) + 2 * al(kMaxP * kMaxP * 8) + al(kMaxP * kMaxP * 8) + al(kMaxP * 8);
+  s += al(4 * 8) + al((n1 / 256 + 2) * 8) + al(n1 * p * 8) + al(n2 * p * 8);
+  s += al((size_t)kGramBlocks * kMaxP * kMaxP * 8) + al(kMaxP * kMaxP * 8);
   s += 2 * al(kMaxP * kMaxP * 8) + al(kMaxP * 8) + al(n1 * r * 8) + al(n2 * r * 8);
   return s;
 }
@@ -895,10 +899,12 @@ int gram(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
   return nblk;
 }
 
-// G = X^T X into w.G (for the small eigenproblems).
-void gram_full(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
-  const int nblk = gram(w, X, n, p, st);
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(cdiv(p * p, 256)), dim3(256), 0, st, w.part, nblk, p, w.G);
+
+void apply2(const double *X1, int64_t n1, const double *M1, double *Xo1, const float *na2, const double *FA,
+            const double *X2, int64_t n2, const double *M2, double *Xo2, int pin, int pout, hipStream_t st) {
+  const int64_t nb1 = cdiv(n1, 4), nb2 = cdiv(n2, 4);
+  hipLaunchKernelGGL(apply2_kernel, dim3((unsigned)(nb1 + nb2)), dim3(256), 0, st, X1, n1, M1, Xo1, na2, FA, X2, n2, M2,
+                     Xo2, pin, pout, nb1);
 }
 
 void apply(const double *X, int64_t n, int pin, const double *M, int pout, double *Xout, hipStream_t st) {
@@ -971,11 +977,8 @@ void ls_solve(const int64_t *ptr, const int32_t *idx, const double *wt, const do
 // (U V^T = Uc diag(sigma) Vc^T). Uc written to Uout, Vc to Vout.
 void canonical(const Ws &w, const double *U, int64_t n1, const double *V, int64_t n2, int r, double *Uout,
                double *Vout, double *sigma, hipStream_t st) {
-  gram_full(w, U, n1, r, st);
-  jacobi_eig(w.G, r, w.W, w.lam, st);
-  hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, r, r, w.Mu, w.Mv, sigma);
-  apply(U, n1, r, w.Mu, r, Uout, st);
-  apply(V, n2, r, w.Mv, r, Vout, st);
+  jacobi_eig(w.part, gram(w, U, n1, r, st), r, r, w.Mu, w.Mv, sigma, st);
+  apply2(U, n1, w.Mu, Uout, nullptr, nullptr, V, n2, w.Mv, Vout, r, r, st);
   hipLaunchKernelGGL(sign_fix_kernel, dim3(r), dim3(256), 0, st, Uout, n1, Vout, n2, r);
 }
 
@@ -1012,12 +1015,8 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   orth(w, w.Y, n2, p, st);
   spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
   // Rayleigh-Ritz: X = R Y; X^T X = W diag(lam) W^T; U0 = X W_r lam^-1/2, V0 = Y W_r
-  gram_full(w, w.X, n1, p, st);
-  jacobi_eig(w.G, p, w.W, w.lam, st);
-  hipLaunchKernelGGL(ritz_maps_kernel, dim3(1), dim3(256), 0, st, w.W, w.lam, p, r, w.Mu, w.Mv, w.sig);
-  apply(w.X, n1, p, w.Mu, r, w.U, st);
-  apply(w.Y, n2, p, w.Mv, r, w.V, st);
-  hipLaunchKernelGGL(trim_kernel, dim3(cdiv(n1, 256)), dim3(256), 0, st, w.U, n1, r, na2, w.FA);
+  jacobi_eig(w.part, gram(w, w.X, n1, p, st), p, r, w.Mu, w.Mv, w.sig, st);
+  apply2(w.X, n1, w.Mu, w.U, na2, w.FA, w.Y, n2, w.Mv, w.V, p, r, st);   // U0 (trimmed), V0
 
   if (T == 0) {
     hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
