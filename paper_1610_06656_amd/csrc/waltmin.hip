@@ -486,9 +486,10 @@ __global__ __launch_bounds__(256) void spmm_kernel(const int64_t *__restrict__ p
                                                    const double *__restrict__ w, const double *__restrict__ mt,
                                                    const uint8_t *__restrict__ sub, int sel,
                                                    const double *__restrict__ Y, int p, int64_t n_out,
-                                                   double *__restrict__ Xout) {
+                                                   const double *__restrict__ Mpost, double *__restrict__ Xout) {
   constexpr int NG = 64 / G;
   __shared__ double red[4 * 64];
+  __shared__ double xs[64];
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
   const int g = lane / G, a = lane % G;
@@ -540,8 +541,21 @@ __global__ __launch_bounds__(256) void spmm_kernel(const int64_t *__restrict__ p
   for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
   red[wave * 64 + lane] = acc;
   __syncthreads();
-  if (wave == 0 && g == 0 && a < p)
-    Xout[o * p + a] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+  if (wave != 0) return;
+  const double x = (g == 0 && a < p) ? ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane] : 0.0;
+  if (!Mpost) {
+    if (g == 0 && a < p) Xout[o * p + a] = x;
+    return;
+  }
+  // Xout row = (sum of the rows) Mpost: the factor's CholeskyQR map, applied
+  // here instead of to the factor before the product (R (Y M) = (R Y) M)
+  if (g == 0 && a < p) xs[a] = x;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (g == 0 && a < p) {
+    double y = 0.0;
+    for (int b = 0; b < p; ++b) y = fma(xs[b], Mpost[b * p + a], y);
+    Xout[o * p + a] = y;
+  }
 }
 
 __global__ void gaussian_block_kernel(int64_t n, int p, uint64_t seed, double *__restrict__ Y) {
@@ -930,21 +944,30 @@ void orth(const Ws &w, double *X, int64_t n, int p, hipStream_t st) {
   cholqr_pass(w, X, n, p, 0.0, X, st);
 }
 
-// One shifted CholeskyQR pass: the span is kept and the columns come out
-// orthonormal up to O(eps cond(X)^2), enough to condition the next solve.
-void orth1(const Ws &w, double *X, int64_t n, int p, hipStream_t st) {
-  cholqr_pass(w, X, n, p, 1e-14, X, st);
+// The map of one shifted CholeskyQR pass (X^T X + shift = L L^T, w.M = L^-T),
+// without applying it: the next sparse product multiplies its output by w.M
+// (span kept; X w.M has orthonormal columns up to O(eps cond(X)^2), enough to
+// condition the next product).
+void orth1_map(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
+  const int nblk = gram(w, X, n, p, st);
+  if (p <= 16)
+    hipLaunchKernelGGL(chol_inv_kernel<16>, dim3(1), dim3(256), 0, st, w.part, nblk, p, 1e-14, w.M);
+  else if (p <= 32)
+    hipLaunchKernelGGL(chol_inv_kernel<32>, dim3(1), dim3(256), 0, st, w.part, nblk, p, 1e-14, w.M);
+  else
+    hipLaunchKernelGGL(chol_inv_kernel<0>, dim3(1), dim3(256), 0, st, w.part, nblk, p, 1e-14, w.M);
 }
 
+// Xout = R Y (CSR side) or R^T Y (CSC side), times Mpost (p x p) when given.
 void spmm(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
-          const double *Y, int p, int64_t n_out, double *Xout, hipStream_t st) {
+          const double *Y, int p, int64_t n_out, const double *Mpost, double *Xout, hipStream_t st) {
   const dim3 grid((unsigned)std::max<int64_t>(1, n_out)), blk(256);
   if (p <= 16)
-    hipLaunchKernelGGL(spmm_kernel<16>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Xout);
+    hipLaunchKernelGGL(spmm_kernel<16>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Mpost, Xout);
   else if (p <= 32)
-    hipLaunchKernelGGL(spmm_kernel<32>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Xout);
+    hipLaunchKernelGGL(spmm_kernel<32>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Mpost, Xout);
   else
-    hipLaunchKernelGGL(spmm_kernel<64>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Xout);
+    hipLaunchKernelGGL(spmm_kernel<64>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Mpost, Xout);
 }
 
 template <int R>
@@ -1005,15 +1028,16 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   // ---- init: subspace iteration on R = w .* P_Omega0(M~)
   hipLaunchKernelGGL(gaussian_block_kernel, dim3(cdiv(n2 * ((p + 3) / 4), 256)), dim3(256), 0, st, n2, p, prm.seed,
                      w.Y);
-  orth1(w, w.Y, n2, p, st);
+  // each sparse product applies the CholeskyQR map of its input (orth1_map)
+  orth1_map(w, w.Y, n2, p, st);
   for (int it = 0; it < iters; ++it) {
-    spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
-    orth1(w, w.X, n1, p, st);
-    spmm(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 0, w.X, p, n2, w.Y, st);
-    if (it + 1 < iters) orth1(w, w.Y, n2, p, st);
+    spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.M, w.X, st);
+    orth1_map(w, w.X, n1, p, st);
+    spmm(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 0, w.X, p, n2, w.M, w.Y, st);
+    if (it + 1 < iters) orth1_map(w, w.Y, n2, p, st);
   }
   orth(w, w.Y, n2, p, st);
-  spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.X, st);
+  spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, nullptr, w.X, st);
   // Rayleigh-Ritz: X = R Y; X^T X = W diag(lam) W^T; U0 = X W_r lam^-1/2, V0 = Y W_r
   jacobi_eig(w.part, gram(w, w.X, n1, p, st), p, r, w.Mu, w.Mv, w.sig, st);
   apply2(w.X, n1, w.Mu, w.U, na2, w.FA, w.Y, n2, w.Mv, w.V, p, r, st);   // U0 (trimmed), V0
