@@ -338,7 +338,7 @@ __device__ __forceinline__ void loop_fp8_stored(const SkArgs &g, const SkWork &w
   constexpr int LT = CPW * W;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int q = lane & 15, gq = lane >> 4;
+  const int gq = lane >> 4;
   const int64_t row_last = w.lend - 1;
   const int64_t lcol = VEC ? (col < w.n - NV ? col : w.n - NV) : col;
   const float *base = w.X + w.lbeg * w.ld;

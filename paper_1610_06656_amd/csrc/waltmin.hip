@@ -618,7 +618,7 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, i
 // Gram tiles are summed in LDS and the r x r system is solved there.
 // R > 0: the instantiation for r = R (RT = 1 only); R = 0: any r of the tile width.
 template <int RT, int R>
-__global__ __launch_bounds__(256, 5) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+__global__ __launch_bounds__(256, RT == 1 ? 5 : 1) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                        const double *__restrict__ w, const double *__restrict__ mt,
                                                        const uint8_t *__restrict__ sub, int sel,
                                                        const double *__restrict__ Q, int r, int64_t n_out,
