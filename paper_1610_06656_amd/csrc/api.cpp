@@ -464,6 +464,17 @@ smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, cons
   return SMP_OK;
 }
 
+// WAltMin on the context's workspace; fa: F_A already on the device (the
+// sampler's, in the same summation order), or null to sum it from na2.
+static smp_status waltmin_call(smp_ctx *ctx, const smp_params *p, const smp_omega *om, const float *na2, double *U,
+                               double *V, double *sigma, const double *fa) {
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.wm, smp::waltmin_ws_bytes(p->n1, p->n2, p->r, om->nnz));
+  if (s != SMP_OK) return s;
+  SMP_HIP(ctx, smp::waltmin_run(*p, *om, na2, U, V, sigma, b.wm.p, ctx->stream, fa));
+  return SMP_OK;
+}
+
 smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, const float *na2, double *U, double *V,
                        double *sigma) {
   if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
@@ -473,11 +484,7 @@ smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, c
   if (om->n1 != p->n1 || om->n2 != p->n2) return fail(ctx, SMP_ERR_INVALID_ARG, "om grid differs from params");
   if (p->omega_mode == SMP_OMEGA_SPLIT && om->nnz > 0 && (!om->sub_csr || !om->sub_csc))
     return fail(ctx, SMP_ERR_INVALID_ARG, "SPLIT mode needs sub_csr and sub_csc");
-  smp_ctx_bufs &b = bufs(ctx);
-  smp_status s = ensure(ctx, b.wm, smp::waltmin_ws_bytes(p->n1, p->n2, p->r, om->nnz));
-  if (s != SMP_OK) return s;
-  SMP_HIP(ctx, smp::waltmin_run(*p, *om, na2, U, V, sigma, b.wm.p, ctx->stream, nullptr));
-  return SMP_OK;
+  return waltmin_call(ctx, p, om, na2, U, V, sigma, nullptr);
 }
 
 smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
@@ -547,7 +554,12 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
   if (s != SMP_OK) return s;
   mark(ctx, kStEstimate, true);
   mark(ctx, kStWaltmin, false);
-  s = smp_waltmin(ctx, &q, &om, na2, U, V, sigma);
+  {
+    smp::SampleWs sws;   // the sampler's F_A (stats[0]) is the trim's
+    s = sample_ws(ctx, n1, n2, sws);
+    if (s != SMP_OK) return s;
+    s = waltmin_call(ctx, &q, &om, na2, U, V, sigma, sws.stats);
+  }
   if (s != SMP_OK) return s;
   mark(ctx, kStWaltmin, true);
   SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -26,14 +26,19 @@ namespace {
 constexpr double kTwo32 = 4294967296.0;
 
 // out[b] = x[256 b] + x[256 b + 1] + ... in index order (binary64, no
-// contraction). One workgroup per block of 256 indices: the block is staged in
+// contraction), for x1 (blocks 0 .. nb1-1 of the grid's work) and then x2
+// into out2. One workgroup per block of 256 indices: the block is staged in
 // LDS with one load per thread, then summed by one thread.
-__global__ __launch_bounds__(256) void block_sums_kernel(const float *__restrict__ x, int64_t n,
-                                                         double *__restrict__ out) {
+__global__ __launch_bounds__(256) void block_sums_kernel(const float *__restrict__ x1, int64_t n1,
+                                                         double *__restrict__ out1, const float *__restrict__ x2,
+                                                         int64_t n2, double *__restrict__ out2) {
 #pragma clang fp contract(off)
   __shared__ float v[256];
-  const int64_t nb = (n + 255) / 256;
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+  const int64_t nb1 = (n1 + 255) / 256, nb = nb1 + (n2 + 255) / 256;
+  for (int64_t bb = blockIdx.x; bb < nb; bb += gridDim.x) {
+    const bool first = bb < nb1;
+    const float *x = first ? x1 : x2;
+    const int64_t n = first ? n1 : n2, b = first ? bb : bb - nb1;
     const int64_t i = b * 256 + threadIdx.x;
     v[threadIdx.x] = i < n ? x[i] : 0.0f;
     __syncthreads();
@@ -41,14 +46,14 @@ __global__ __launch_bounds__(256) void block_sums_kernel(const float *__restrict
       const int cnt = (int)std::min<int64_t>(256, n - b * 256);
       double s = 0.0;
       for (int u = 0; u < cnt; ++u) s = s + (double)v[u];
-      out[b] = s;
+      (first ? out1 : out2)[b] = s;
     }
     __syncthreads();
   }
 }
 
-inline unsigned block_sums_grid(int64_t n) {
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+inline unsigned block_sums_grid(int64_t n1, int64_t n2) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n1 + 255) / 256 + (n2 + 255) / 256, 65536));
 }
 
 __global__ void totals_kernel(const double *__restrict__ ba, int64_t nba, const double *__restrict__ bb,
@@ -64,11 +69,32 @@ __global__ void totals_kernel(const double *__restrict__ ba, int64_t nba, const 
   stats[3] = (2.0 * (double)n1) * fb;
 }
 
+// alpha_i = na2_i / den_A, beta_j = nb2_j / den_B. Every workgroup forms
+// F_A, F_B and the denominators from the block sums itself, exactly as
+// totals_kernel does (sequential over the blocks), and workgroup 0 stores them
+// in stats.
 __global__ void marginals_kernel(const float *__restrict__ na2, const float *__restrict__ nb2, int64_t n1,
-                                 int64_t n2, const double *__restrict__ stats, double *__restrict__ alpha,
-                                 double *__restrict__ beta) {
+                                 int64_t n2, const double *__restrict__ ba, int64_t nba,
+                                 const double *__restrict__ bb, int64_t nbb, double *__restrict__ stats,
+                                 double *__restrict__ alpha, double *__restrict__ beta) {
 #pragma clang fp contract(off)
-  const double den_a = stats[2], den_b = stats[3];
+  __shared__ double den[2];
+  if (threadIdx.x == 0) {
+    double fa = 0.0, fb = 0.0;
+    for (int64_t b = 0; b < nba; ++b) fa = fa + ba[b];
+    for (int64_t b = 0; b < nbb; ++b) fb = fb + bb[b];
+    const double da = (2.0 * (double)n2) * fa, db = (2.0 * (double)n1) * fb;
+    den[0] = da;
+    den[1] = db;
+    if (blockIdx.x == 0) {
+      stats[0] = fa;
+      stats[1] = fb;
+      stats[2] = da;
+      stats[3] = db;
+    }
+  }
+  __syncthreads();
+  const double den_a = den[0], den_b = den[1];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n1 + n2;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (i < n1)
@@ -256,12 +282,10 @@ inline unsigned grid_for(int64_t items, int per_block) {
 hipError_t sample_prepare(const float *na2, const float *nb2, int64_t n1, int64_t n2, SampleWs &ws,
                           hipStream_t st) {
   const int64_t nba = (n1 + 255) / 256, nbb = (n2 + 255) / 256;
-  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n1)), dim3(256), 0, st, na2, n1, ws.blocks);
-  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n2)), dim3(256), 0, st, nb2, n2, ws.blocks + nba);
-  hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, st, ws.blocks, nba, ws.blocks + nba, nbb, n1, n2,
-                     ws.stats);
-  hipLaunchKernelGGL(marginals_kernel, dim3(grid_for(n1 + n2, 256)), dim3(256), 0, st, na2, nb2, n1, n2, ws.stats,
-                     ws.alpha, ws.beta);
+  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n1, n2)), dim3(256), 0, st, na2, n1, ws.blocks, nb2, n2,
+                     ws.blocks + nba);
+  hipLaunchKernelGGL(marginals_kernel, dim3(grid_for(n1 + n2, 256)), dim3(256), 0, st, na2, nb2, n1, n2, ws.blocks,
+                     nba, ws.blocks + nba, nbb, ws.stats, ws.alpha, ws.beta);
   return hipGetLastError();
 }
 
@@ -289,7 +313,8 @@ hipError_t sample_fill(const SampleWs &ws, int64_t n1, int64_t n2, double m, uin
 // the block sums) into out[0]; out must hold 4 doubles.
 hipError_t fixed_total(const float *x, int64_t n, double *blocks, double *out, hipStream_t st) {
   const int64_t nb = (n + 255) / 256;
-  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n)), dim3(256), 0, st, x, n, blocks);
+  hipLaunchKernelGGL(block_sums_kernel, dim3(block_sums_grid(n, 0)), dim3(256), 0, st, x, n, blocks,
+                     (const float *)nullptr, (int64_t)0, (double *)nullptr);
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(64), 0, st, blocks, nb, blocks, (int64_t)0, n, n, out);
   return hipGetLastError();
 }

@@ -105,6 +105,7 @@ hipError_t estimate_run(const float *At, const float *Bt, const float *na2, cons
 // ---- WAltMin -------------------------------------------------------------------
 size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t nnz);
 hipError_t waltmin_run(const smp_params &p, const smp_omega &om, const float *na2, double *U, double *V,
-                       double *sigma, void *ws, hipStream_t st, int *status_flag_host);
+                       double *sigma, void *ws, hipStream_t st,
+                       const double *fa_in);   // F_A on the device, or null to sum it from na2
 
 }  // namespace smp

@@ -1013,7 +1013,7 @@ size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t /*nnz*/) {
 }
 
 hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *na2, double *Uout, double *Vout,
-                       double *sigma, void *wsbase, hipStream_t st, int * /*status*/) {
+                       double *sigma, void *wsbase, hipStream_t st, const double *fa_in) {
   const int64_t n1 = om.n1, n2 = om.n2;
   const int r = prm.r, T = prm.T;
   const int p = std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample)));
@@ -1023,7 +1023,12 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   const uint8_t *scsr = split ? om.sub_csr : nullptr;
   const uint8_t *scsc = split ? om.sub_csc : nullptr;
 
-  fixed_total(na2, n1, w.blocks, w.FA, st);
+  // F_A (the squared Frobenius norm of A in the sampler's fixed order): given, or summed here
+  const double *FA = fa_in;
+  if (!FA) {
+    fixed_total(na2, n1, w.blocks, w.FA, st);
+    FA = w.FA;
+  }
 
   // ---- init: subspace iteration on R = w .* P_Omega0(M~)
   hipLaunchKernelGGL(gaussian_block_kernel, dim3(cdiv(n2 * ((p + 3) / 4), 256)), dim3(256), 0, st, n2, p, prm.seed,
@@ -1040,7 +1045,7 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
   spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, nullptr, w.X, st);
   // Rayleigh-Ritz: X = R Y; X^T X = W diag(lam) W^T; U0 = X W_r lam^-1/2, V0 = Y W_r
   jacobi_eig(w.part, gram(w, w.X, n1, p, st), p, r, w.Mu, w.Mv, w.sig, st);
-  apply2(w.X, n1, w.Mu, w.U, na2, w.FA, w.Y, n2, w.Mv, w.V, p, r, st);   // U0 (trimmed), V0
+  apply2(w.X, n1, w.Mu, w.U, na2, FA, w.Y, n2, w.Mv, w.V, p, r, st);   // U0 (trimmed), V0
 
   if (T == 0) {
     hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
