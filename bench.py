@@ -327,7 +327,7 @@ def main():
             "flops_per_launch": flops}),
         "fp8": dict(leg_summary(fp8), roofline={
             "bound": "hbm", "achieved": round(in_bytes / (sk_fp8 / 1e3) / 1e9, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(in_bytes / (sk_fp8 / 1e3) / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
+            "frac": round(in_bytes / (sk_fp8 / 1e3) / 1e9 / PEAK_HBM_GBPS, 4), "traffic": recorded_traffic("sketch_fp8_c2_traffic"),
             "kernel": "FP8 sketch pass: pi_store_fp8_kernel, then sketch_fp8_stored_kernel "
                       "(v_mfma_scale_f32_16x16x128_f8f6f4) main and tail launch, timed together",
             "kernel_ms": round(sk_fp8, 4), "bytes_per_launch": in_bytes,
