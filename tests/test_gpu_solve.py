@@ -82,6 +82,19 @@ def test_solve_a_equals_b(api, ctx):
     assert abs(e_gpu - e_ora) <= 1e-4 * e_ora
 
 
+def test_solve_empty_omega(api, ctx):
+    """No sampled entry (tiny m): the estimate is the zero matrix and the
+    rank-r fit is zero, as in the oracle; no error, finite outputs."""
+    A, B, Ad, Bd = latent(500, 50, 60, R=3)
+    log("solve empty Omega")
+    U, s, V, p = _run_gpu(api, ctx, Ad, Bd, 20, 3, 4, m=1e-6)
+    ref = oso.smp_pca(A.numpy(), B.numpy(), 3, 20, p.m, 4, SEED)
+    assert ref["omega"].nnz == 0
+    assert np.array_equal(s, ref["sigma"])                  # both exactly zero
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(V))
+    assert not np.any((U * s[None, :]) @ V.T)
+
+
 def test_solve_deterministic(api, ctx):
     _, _, Ad, Bd = latent(5000, 300, 280, R=5)
     r1 = _run_gpu(api, ctx, Ad, Bd, 64, 5, 5)

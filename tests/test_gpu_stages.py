@@ -171,6 +171,7 @@ SAMPLE_CASES = {
     "zero_norms": dict(n1=64, n2=66, m=None, r=4, zero_a=(0, 5), zero_b=(3,)),
     "split_T3": dict(n1=150, n2=90, m=None, r=4, T=3, split=True),
     "wide": dict(n1=1000, n2=2047, m=None, r=10),
+    "empty": dict(n1=50, n2=60, m=1e-6, r=2),          # no entry kept
 }
 
 
@@ -189,6 +190,7 @@ def test_sample_bit_exact(api, ctx, name):
     torch.cuda.synchronize()
     ref = osa.sample(na2.astype(np.float64), nb2.astype(np.float64), p.m, p.seed, T=T, split=split)
     assert nnz == ref.nnz
+    assert (ref.nnz == 0) == (name == "empty")
     h = omega_to_host(om)
     assert np.array_equal(h["rows"], ref.rows) and np.array_equal(h["cols"], ref.cols)
     assert np.array_equal(h["w"].view(np.uint64), ref.w.view(np.uint64))      # bitwise

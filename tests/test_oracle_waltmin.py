@@ -244,3 +244,16 @@ def test_pipeline_a_equals_b_pca():
     assert res["At"] is res["Bt"]
     e = evaluate.relative_error(AtA, res["Uc"], res["sigma"], res["Vc"])
     assert e < 0.1
+
+
+def test_empty_omega_gives_zero_approximation():
+    """Degenerate case of Alg. 1: with no sampled entry R_Omega(M~) is the zero
+    matrix, so the rank-r fit of Alg. 2 is zero (sigma = 0) and every
+    least-squares row has no equations (zero solution)."""
+    A, B = smp_inputs.latent_pair(500, 50, 60, 3, 0.1, 0.5, 7)
+    A, B = A.numpy(), B.numpy()
+    res = solve.smp_pca(A, B, 3, 20, 1e-6, 4, seed=7)
+    assert res["omega"].nnz == 0
+    assert np.array_equal(res["sigma"], np.zeros(3))
+    assert np.all(np.isfinite(res["Uc"])) and np.all(np.isfinite(res["Vc"]))
+    assert not np.any(res["U"])                            # no equations: zero rows
