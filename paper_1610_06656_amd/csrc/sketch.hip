@@ -315,7 +315,8 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   g.seed = seed;
   g.part = part;
   g.npart = npart;
-  auto launch = [&](KernelPtr kern, int64_t r0, int64_t nrows, int splits, int64_t rps, int s_base) {
+  auto launch = [&](KernelPtr kern, int64_t r0, int64_t nrows, int splits, int64_t rps, int s_base, int extra = 0,
+                    int unit = 0) {
     g.row0 = r0;
     // stored Pi: the launch's first row r0 is a whole number of 32-row blocks past row0
     g.pi = pl.pi_stored ? static_cast<const char *>(pi_buf) +
@@ -324,6 +325,8 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
     g.rows = nrows;
     g.S = splits;
     g.rows_per_split = rps;
+    g.split_extra = extra;
+    g.split_unit = unit;
     g.s_base = s_base;
     const int64_t nlog = (int64_t)g.kt * (g.a.ntiles + g.b.ntiles) * splits;
     const int64_t grid = (nlog + 7) / 8 * 8;
@@ -345,10 +348,11 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
     return launch(kern, row0, rows, S, rps, 0);
   }
 
-  // BF16 / FP8: a main launch over S splits of whole Pi blocks, and a tail launch
-  // (one split, clamped) for the rows left over, into partial slot S. The
-  // tail launch also runs with no rows, so that a one-shot pass stores zeros
-  // in that slot.
+  // BF16 / FP8: a main launch over S splits holding every whole Pi block (the
+  // first nblk mod S splits one block more than the others), and a tail launch
+  // (one split, clamped) for the rows past the last whole block, into partial
+  // slot S. The tail launch also runs with no rows, so that a one-shot pass
+  // stores zeros in that slot.
   if (pl.pi_stored) {
     const hipError_t e = pi_store(pl, seed, row0, rows, k, pi_buf, st);
     if (e != hipSuccess) return e;
@@ -357,10 +361,12 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   KernelPtr kmain = reinterpret_cast<KernelPtr>(vec ? pl.kernel : pl.kernel_scalar);
   KernelPtr ktail = reinterpret_cast<KernelPtr>(vec ? pl.kernel_clamp : pl.kernel_scalar);
   if (!kmain || !ktail) return hipErrorInvalidValue;
-  const int64_t rps = rows / S / pl.kc * pl.kc;
-  const int64_t main_rows = rps * S;
+  const int64_t nblk = rows / pl.kc;
+  const int64_t rps = nblk / S * pl.kc;
+  const int extra = (int)(nblk % S);
+  const int64_t main_rows = nblk * pl.kc;
   if (main_rows > 0 || !accumulate) {   // with no whole block the one-shot pass still stores zero partials
-    const hipError_t e = launch(kmain, row0, main_rows, S, rps, 0);
+    const hipError_t e = launch(kmain, row0, main_rows, S, rps, 0, extra, pl.kc);
     if (e != hipSuccess) return e;
   }
   const int64_t tail = rows - main_rows;

@@ -21,6 +21,8 @@ struct SkArgs {
   SkMat a, b;
   int64_t row0, rows, rows_per_split, ntot;
   int k, kpad, kt, mt_total, S;
+  int split_extra;  // splits 0 .. split_extra-1 hold split_unit rows more than rows_per_split
+  int split_unit;
   int s_base;       // partial slot of split 0
   int accumulate;   // 1: add into the partials (streaming pushes); 0: store them (one-shot pass)
   uint64_t seed;
@@ -64,8 +66,10 @@ __device__ __forceinline__ bool sk_decode(const SkArgs &g, SkWork &w) {
   w.n = m.n;
   w.col_base = m.col_base;
   w.vec_ok = m.vec_ok != 0;
-  w.lbeg = (int64_t)w.s * g.rows_per_split;
-  w.lend = w.lbeg + g.rows_per_split < g.rows ? w.lbeg + g.rows_per_split : g.rows;
+  const int longer = w.s < g.split_extra;
+  w.lbeg = (int64_t)w.s * g.rows_per_split + (int64_t)(longer ? w.s : g.split_extra) * g.split_unit;
+  const int64_t span = g.rows_per_split + (longer ? g.split_unit : 0);
+  w.lend = w.lbeg + span < g.rows ? w.lbeg + span : g.rows;
   return true;
 }
 
