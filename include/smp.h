@@ -200,7 +200,10 @@ smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, c
  * of the last call: [0] sketch kernel, [1] sketch reduction, [2] sampling,
  * [3] estimate, [4] WAltMin (init + iterations + canonical form). Stages that
  * did not run report 0. n is the capacity of ms (up to 5 are written).
- * Enabling costs one event pair per stage; it does not synchronise more. */
+ * enable: 0 off, 1 every stage, 2 the sketch stage only (the others report 0);
+ * other values are SMP_ERR_INVALID_ARG. Changing the level forgets the stages
+ * recorded before. Each timed stage costs one event pair on the stream (about
+ * 10 us of idle GPU at each stage boundary); it does not synchronise more. */
 smp_status smp_set_timing(smp_ctx *ctx, int enable);
 smp_status smp_stage_times(smp_ctx *ctx, float *ms, int n);
 

@@ -191,7 +191,8 @@ class Context:
                                          _ptr(sigma, torch.float64, "sigma")))
 
     def smp_set_timing(self, enable=True):
-        self._check(self.lib.smp_set_timing(self.h, 1 if enable else 0))
+        """True or 1: every stage; 2: the sketch stage only; False or 0: off."""
+        self._check(self.lib.smp_set_timing(self.h, int(enable)))
 
     def smp_stage_times(self):
         """ms of the last call's stages: sketch kernel, sketch reduction,

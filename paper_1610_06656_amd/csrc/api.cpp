@@ -111,8 +111,10 @@ size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 enum Stage { kStSketch = 0, kStFinish = 1, kStSample = 2, kStEstimate = 3, kStWaltmin = 4 };
 
+bool timed(const smp_ctx *ctx, int s) { return ctx->timing == 1 || (ctx->timing == 2 && s == kStSketch); }
+
 void mark(smp_ctx *ctx, Stage s, bool end) {
-  if (!ctx->timing) return;
+  if (!timed(ctx, s)) return;
   hipEventRecord(ctx->events[2 * s + (end ? 1 : 0)], ctx->stream);
   if (end) ctx->recorded[s] = true;
 }
@@ -212,9 +214,11 @@ smp_status smp_set_stream(smp_ctx *ctx, void *hip_stream) {
 
 smp_status smp_set_timing(smp_ctx *ctx, int enable) {
   if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  if (enable < 0 || enable > 2) return fail(ctx, SMP_ERR_INVALID_ARG, "timing level must be 0, 1 or 2");
   if (enable && !ctx->events[0])
     for (hipEvent_t &e : ctx->events) SMP_HIP(ctx, hipEventCreate(&e));
-  ctx->timing = enable != 0;
+  ctx->timing = enable;
+  for (bool &r : ctx->recorded) r = false;   // no stage of an earlier setting is reported
   return SMP_OK;
 }
 
@@ -222,7 +226,7 @@ smp_status smp_stage_times(smp_ctx *ctx, float *ms, int n) {
   if (!ctx || !ms || n < 0) return fail(ctx, SMP_ERR_INVALID_ARG, "ctx or ms is NULL");
   for (int s = 0; s < 5 && s < n; ++s) {
     ms[s] = 0.0f;
-    if (ctx->timing && ctx->recorded[s]) {
+    if (timed(ctx, s) && ctx->recorded[s]) {
       SMP_HIP(ctx, hipEventSynchronize(ctx->events[2 * s + 1]));
       SMP_HIP(ctx, hipEventElapsedTime(&ms[s], ctx->events[2 * s], ctx->events[2 * s + 1]));
     }

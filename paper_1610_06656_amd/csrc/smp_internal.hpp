@@ -17,8 +17,9 @@ struct smp_ctx {
   size_t ws_bytes = 0;
   // small pinned host buffer for the few readbacks
   int64_t *host_pinned = nullptr;
-  // stage timing: events[2*s] / events[2*s+1] bracket stage s
-  bool timing = false;
+  // stage timing: events[2*s] / events[2*s+1] bracket stage s; timing is
+  // 0 (off), 1 (every stage) or 2 (the sketch stage only)
+  int timing = 0;
   hipEvent_t events[10] = {};
   bool recorded[5] = {};
 };

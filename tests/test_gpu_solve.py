@@ -170,3 +170,22 @@ def test_c2_end_to_end_matches_oracle(api, ctx):
     e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
     log(f"  e_gpu={e_gpu:.6e} e_oracle={e_ora:.6e} |Omega|={ref['omega'].nnz}")
     assert abs(e_gpu - e_ora) <= 1e-4 * e_ora
+
+
+def test_stage_timing_levels(api, ctx):
+    """Level 1 times every stage, level 2 the sketch stage only; other levels
+    are rejected."""
+    _, _, Ad, Bd = latent(2000, 200, 200, R=5)
+    ctx.smp_set_timing(1)
+    _run_gpu(api, ctx, Ad, Bd, 50, 5, 4)
+    t1 = ctx.smp_stage_times()
+    assert all(v > 0 for v in t1.values())
+    ctx.smp_set_timing(2)
+    _run_gpu(api, ctx, Ad, Bd, 50, 5, 4)
+    t2 = ctx.smp_stage_times()
+    assert t2["sketch"] > 0 and all(v == 0 for k, v in t2.items() if k != "sketch")
+    with pytest.raises(api.SmpError) as e:
+        ctx.smp_set_timing(3)
+    assert e.value.status == 1
+    ctx.smp_set_timing(0)
+    assert all(v == 0 for v in ctx.smp_stage_times().values())
