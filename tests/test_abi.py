@@ -102,6 +102,9 @@ def test_null_pointers_rejected_before_launch(lib):
     p = _params()
     assert lib.smp_sketch(None, ctypes.byref(p), None, 0, None, 0, None, None, None, None) == _lib.SMP_ERR_INVALID_ARG
     assert lib.smp_solve(None, ctypes.byref(p), None, 0, None, 0, None, None, None) == _lib.SMP_ERR_INVALID_ARG
+    assert lib.smp_set_timing(None, 1) == _lib.SMP_ERR_INVALID_ARG
+    ms = (ctypes.c_float * 5)()
+    assert lib.smp_stage_times(None, ms, 5) == _lib.SMP_ERR_INVALID_ARG
 
 
 @pytest.mark.skipif(gpu_available(), reason="checks the no-device path")
