@@ -197,6 +197,8 @@ SOLVE_CASES = {
     "c1": dict(d=2000, n1=200, n2=200, R=5, k=50, r=5, T=10),
     "ragged": dict(d=1037, n1=77, n2=131, R=3, k=37, r=3, T=8),
     "k400_r10": dict(d=20000, n1=300, n2=260, R=10, k=400, r=10, T=10),
+    "tiny_d1": dict(d=1, n1=3, n2=4, R=1, k=2, r=1, T=3),        # no whole 32-row block: tail launch only
+    "single_row": dict(d=64, n1=1, n2=5, R=1, k=3, r=1, T=2),
 }
 
 
@@ -205,7 +207,7 @@ def test_solve_bf16_matches_oracle(api, ctx, name):
     c = SOLVE_CASES[name]
     log(f"bf16 solve {name} {c}")
     A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=c["R"])
-    m = api.default_m(c["n1"], c["n2"], c["r"])
+    m = api.default_m(c["n1"], c["n2"], c["r"]) if min(c["n1"], c["n2"]) > 1 else 50.0
     p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], m=m, prec=api.SMP_PREC_BF16,
                         init_iters=40)
     U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=DEV)
@@ -218,7 +220,9 @@ def test_solve_bf16_matches_oracle(api, ctx, name):
     e_gpu = oev.relative_error(AtB, U.cpu().numpy(), s.cpu().numpy(), V.cpu().numpy())
     e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
     log(f"  e_gpu={e_gpu:.6e} e_oracle_bf16={e_ora:.6e}")
-    assert abs(e_gpu - e_ora) <= 1e-3 * e_ora
+    # an exactly low-rank product (the rank-1 cases) leaves errors near FP32
+    # rounding on both sides, which the relative term alone does not resolve
+    assert abs(e_gpu - e_ora) <= 1e-3 * e_ora + 1e-6
 
 
 def test_c2_bf16_solve_error_against_fp64_oracle(api, ctx):
