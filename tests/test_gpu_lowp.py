@@ -339,3 +339,33 @@ def test_solve_fp8_matches_oracle_and_reports_error(api, ctx):
     e8_ora = oev.relative_error(AtB, ref8["Uc"], ref8["sigma"], ref8["Vc"])
     log(f"  e_fp8={e8:.6e} e_oracle_fp8={e8_ora:.6e} e_fp32={e32:.6e}")
     assert abs(e8 - e8_ora) <= 5e-3 * e8_ora
+
+
+FP8_SOLVE_CASES = {
+    "ragged": dict(d=1037, n1=77, n2=131, R=3, k=37, r=3, T=8),
+    "tiny_d1": dict(d=1, n1=3, n2=4, R=1, k=2, r=1, T=3),        # no whole 32-row block: tail launch only
+    "single_row": dict(d=64, n1=1, n2=5, R=1, k=3, r=1, T=2),
+}
+
+
+@pytest.mark.parametrize("name", list(FP8_SOLVE_CASES))
+def test_solve_fp8_small_and_degenerate(api, ctx, name):
+    """FP8 solve against the oracle's FP8 pipeline on a ragged shape and the
+    degenerate ones (a single data row, a single column of A)."""
+    c = FP8_SOLVE_CASES[name]
+    log(f"fp8 solve {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=c["R"])
+    m = api.default_m(c["n1"], c["n2"], c["r"]) if min(c["n1"], c["n2"]) > 1 else 50.0
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], m=m, prec=api.SMP_PREC_FP8,
+                        init_iters=40)
+    U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=DEV)
+    V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=DEV)
+    s = torch.empty(c["r"], dtype=torch.float64, device=DEV)
+    ctx.smp_solve(p, Ad, Bd, U, V, s)
+    torch.cuda.synchronize()
+    ref = oso.smp_pca(A.numpy(), B.numpy(), c["r"], c["k"], p.m, c["T"], SEED, sketch_fmt="fp8")
+    AtB = oev.product(A.numpy(), B.numpy())
+    e_gpu = oev.relative_error(AtB, U.cpu().numpy(), s.cpu().numpy(), V.cpu().numpy())
+    e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
+    log(f"  e_gpu={e_gpu:.6e} e_oracle_fp8={e_ora:.6e}")
+    assert abs(e_gpu - e_ora) <= 5e-3 * e_ora + 1e-6
