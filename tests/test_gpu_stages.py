@@ -216,10 +216,13 @@ def test_sample_capacity_error_reports_size(api, ctx):
 @pytest.mark.parametrize("name,d,n1,n2,k,m", [("c1_tiles", 2000, 200, 200, 50, None),
                                              ("ragged_tiles", 900, 77, 131, 37, None),
                                              ("k400_tiles", 5000, 120, 90, 400, None),
+                                             ("mixed_blocks", 1000, 600, 700, 40, 40000.0),
                                              ("sparse_gather", 1000, 600, 700, 40, 2000.0)])
 def test_estimate_parity(api, ctx, name, d, n1, n2, k, m):
     """Dense grids take the 64 x 64 MFMA tile path, sparse grids (Omega below
-    1/32 of the grid) the gather path; both must give the oracle's values."""
+    1/32 of the grid) the gather path; both must give the oracle's values.
+    "mixed_blocks" covers about 8% of the grid, dense in the heavy leading
+    rows and sparse elsewhere."""
     log(f"estimate {name}")
     A, B, _, _ = latent(d, n1, n2)
     oAt, oBt, ona2, onb2 = osk.sketch(A.numpy(), B.numpy(), SEED, k)
