@@ -60,7 +60,8 @@ typedef enum smp_status {
   SMP_ERR_DEVICE = 3,       /* a HIP runtime call or kernel failed */
   SMP_ERR_NUMERIC = 4,      /* non-finite input or factorisation failure */
   SMP_ERR_CAPACITY = 5,     /* caller buffer too small; the required size is reported */
-  SMP_ERR_STATE = 6         /* call out of order (e.g. push after end) */
+  SMP_ERR_STATE = 6,        /* call out of order (e.g. push after end) */
+  SMP_ERR_BUSY = 7          /* admission refused: the job cannot start now (smp_server_try_submit) */
 } smp_status;
 
 typedef enum smp_precision {
@@ -170,7 +171,10 @@ void smp_sketch_free(smp_sketch_state *st);
  * sequentially in blocks of 256, then over the blocks; den = (2 n2) F_A;
  * alpha_i = na2_i/den; q = m (alpha_i + beta_j); q^ = min(1,q)); (i,j) is kept
  * iff coin(i,j) < floor(q^ 2^32). Synchronises the stream once. If |Omega| >
- * cap, returns SMP_ERR_CAPACITY with om->nnz = |Omega| and no entries written. */
+ * cap, returns SMP_ERR_CAPACITY with om->nnz = |Omega| and no entries written.
+ * If ||A||_F^2 or ||B||_F^2 (the sums of na2, nb2) is not finite - a NaN or
+ * Inf in A or B, or a squared norm beyond the FP32 range - returns
+ * SMP_ERR_NUMERIC and writes no entries. */
 smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const float *nb2, smp_omega *om);
 
 /* ---- a3 (rescale) + a5: estimates on Omega (Eq. (2)) -------------------------
@@ -209,7 +213,8 @@ smp_status smp_stage_times(smp_ctx *ctx, float *ms, int n);
 
 /* ---- the whole of Alg. 1 -----------------------------------------------------
  * smp_sketch -> smp_sample -> smp_estimate -> smp_waltmin with library-owned
- * intermediates. Outputs as smp_waltmin. B may equal A (or SMP_B_IS_A). */
+ * intermediates. Outputs as smp_waltmin. B may equal A (or SMP_B_IS_A).
+ * Non-finite input: SMP_ERR_NUMERIC (see smp_sample), U and V untouched. */
 smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
                      double *U, double *V, double *sigma);
 
@@ -218,9 +223,13 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
  * own context, HIP stream and workspace, so the kernels of different jobs
  * overlap on the device (continuous batching: a job submitted while others
  * run starts as soon as a worker is free and the HBM budget allows). Jobs are
- * admitted in submission order while the sum of the library workspace of the
- * running jobs (smp_workspace_size) stays within `hbm_budget` bytes; a job
- * larger than the budget runs when nothing else does. 0 means no budget.
+ * admitted in submission order while the device memory in use stays within
+ * `hbm_budget` bytes. Memory in use = the workspace every worker's context
+ * holds (a worker keeps its buffers between jobs; while it runs a job, at
+ * least that job's smp_workspace_size) + the inputs and outputs of the
+ * running jobs (d*lda*4 + d*ldb*4 unless B is A, + (n1+n2+1)*r*8). A job
+ * larger than the budget runs when nothing else does, and its worker then
+ * releases its workspace. 0 means no budget (workers keep their buffers).
  * The caller owns every job's inputs and outputs (device memory of the
  * server's device) and keeps them alive and untouched until the job is
  * waited for. Results are the same as smp_solve of the job alone.
@@ -238,7 +247,8 @@ typedef struct smp_server_stats {
   int64_t submitted, completed, failed;
   int32_t max_running;        /* most jobs running at once */
   int32_t workers;
-  int64_t max_budget_in_use;  /* largest sum of admitted workspace (bytes) */
+  int64_t max_budget_in_use;  /* largest memory in use at an admission (bytes, as defined above) */
+  int64_t refused;            /* smp_server_try_submit calls answered SMP_ERR_BUSY */
 } smp_server_stats;
 
 /* workers in [1, 16]. Creates the worker threads and their contexts. */
@@ -247,6 +257,14 @@ smp_status smp_server_create(int device, int workers, size_t hbm_budget, smp_ser
  * returns its id. Does not block on the GPU. */
 smp_status smp_server_submit(smp_server *s, const smp_params *p, const float *A, int64_t lda, const float *B,
                              int64_t ldb, double *U, double *V, double *sigma, uint64_t *job_id);
+/* Admission without queueing, for callers that would rather retry or route
+ * the job elsewhere than wait: queues the job (as smp_server_submit) only if
+ * it can start at once - no job waits ahead of it, a worker is free, and
+ * either nothing runs or the memory in use with it stays within the budget -
+ * else returns SMP_ERR_BUSY and queues nothing (stats.refused counts these).
+ * Argument checks as smp_server_submit. */
+smp_status smp_server_try_submit(smp_server *s, const smp_params *p, const float *A, int64_t lda, const float *B,
+                                 int64_t ldb, double *U, double *V, double *sigma, uint64_t *job_id);
 /* Blocks until the job has finished; fills *res (may be NULL) and forgets the
  * job. SMP_ERR_INVALID_ARG for an unknown or already waited id. Each id is
  * waited for once, by one thread (different ids may be waited for from

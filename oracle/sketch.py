@@ -32,16 +32,6 @@ def pi_block(seed, k, l0, l1):
     return gaussian_block(seed, k, l0, l1) / np.sqrt(float(k))
 
 
-def column_norms2(X, chunk=65536):
-    """Squared L2 norm of every column of X (d x n), FP64 (Alg. 1 step 2)."""
-    X = np.asarray(X)
-    out = np.zeros(X.shape[1], dtype=np.float64)
-    for l0 in range(0, X.shape[0], chunk):
-        xc = np.asarray(X[l0:l0 + chunk], dtype=np.float64)
-        out += np.einsum("li,li->i", xc, xc)
-    return out
-
-
 def sketch(A, B, seed, k, chunk=8192):
     """Single pass: returns (At, Bt, na2, nb2).
 

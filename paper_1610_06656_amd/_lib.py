@@ -17,6 +17,7 @@ SMP_ERR_DEVICE = 3
 SMP_ERR_NUMERIC = 4
 SMP_ERR_CAPACITY = 5
 SMP_ERR_STATE = 6
+SMP_ERR_BUSY = 7
 
 SMP_PREC_FP32 = 0
 SMP_PREC_BF16 = 1
@@ -54,7 +55,7 @@ class SmpJobResult(ctypes.Structure):
 class SmpServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("max_running", ctypes.c_int32), ("workers", ctypes.c_int32),
-                ("max_budget_in_use", ctypes.c_int64)]
+                ("max_budget_in_use", ctypes.c_int64), ("refused", ctypes.c_int64)]
 
 
 EXPORTS = {
@@ -93,6 +94,9 @@ EXPORTS = {
     "smp_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "smp_server_try_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "smp_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(SmpJobResult)]),
     "smp_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "smp_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpServerStats)]),

@@ -11,6 +11,7 @@ import torch
 from . import _lib
 from ._lib import SmpJobResult, SmpOmega, SmpParams, SmpServerStats
 from ._lib import SMP_B_IS_A, SMP_OMEGA_REUSE, SMP_OMEGA_SPLIT, SMP_PREC_BF16, SMP_PREC_FP32, SMP_PREC_FP8  # noqa: F401
+from ._lib import SMP_ERR_BUSY, SMP_ERR_NUMERIC  # noqa: F401
 
 
 class SmpError(RuntimeError):
@@ -247,6 +248,25 @@ class Server:
                                         _ptr(sigma, torch.float64, "sigma"), ctypes.byref(jid))
         if st != 0:
             raise SmpError(st, "smp_server_submit rejected the job")
+        self._held[jid.value] = (p, A, B, U, V, sigma)
+        return jid.value
+
+    def try_submit(self, p, A, B, U, V, sigma=None):
+        """Queue the job only if it can start at once (smp_server_try_submit);
+        returns its id, or None when the server answers SMP_ERR_BUSY."""
+        if A.stride(1) != 1 or (B is not None and B.stride(1) != 1):
+            raise ValueError("A and B must have unit column stride")
+        Bp = B if B is not None else A
+        torch.cuda.current_stream(self.device).synchronize()
+        jid = ctypes.c_uint64()
+        st = self.lib.smp_server_try_submit(self.h, ctypes.byref(p), _ptr(A, torch.float32, "A", dense=False),
+                                            A.stride(0), _ptr(Bp, torch.float32, "B", dense=False), Bp.stride(0),
+                                            _ptr(U, torch.float64, "U"), _ptr(V, torch.float64, "V"),
+                                            _ptr(sigma, torch.float64, "sigma"), ctypes.byref(jid))
+        if st == _lib.SMP_ERR_BUSY:
+            return None
+        if st != 0:
+            raise SmpError(st, "smp_server_try_submit rejected the job")
         self._held[jid.value] = (p, A, B, U, V, sigma)
         return jid.value
 

@@ -60,25 +60,33 @@ std::string check(const smp_params *p) {
   return "";
 }
 
+// Rows one FP32 accumulator of the FP32 pass sums at most. Summing N random-
+// sign products in FP32 leaves a relative error of about 2^-24 sqrt(N / 8)
+// (the 16x16x4 MFMA adds 4 products per accumulation); 32,768 rows keep it
+// near 4e-6, below the 1e-5 per-column bound, whatever d is.
+constexpr int64_t kFp32RowsPerSplit = 32768;
+
 // Number of d-splits S of the sketch pass. The kt * tiles * S workgroups run
 // in ceil(total / slots) rounds on the slots the device holds at once; the
 // S partial sketches are written once and read once by the reduction. S
 // minimises (streaming time with the last round's idle slots) + (partial
 // traffic), both relative to one perfectly balanced read of the input:
 //   cost(S) = rounds * slots / total + 2 S kpad / d,
-// with at least 256 rows per split.
+// with at least 256 rows per split and, for the FP32 pass, at most
+// kFp32RowsPerSplit.
 int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
   const int64_t tiles = (n1 + pl.ncol_tile - 1) / pl.ncol_tile + (n2 + pl.ncol_tile - 1) / pl.ncol_tile;
   const int64_t per = (int64_t)pl.kt * tiles;
   const int64_t slots = smp::sketch_slots(pl);
-  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(256, d / std::max(256, 2 * pl.kc)));
+  const int64_t smin = pl.prec == SMP_PREC_FP32 ? (d + kFp32RowsPerSplit - 1) / kFp32RowsPerSplit : 1;
+  const int64_t smax = std::max<int64_t>(smin, std::min<int64_t>(256, d / std::max(256, 2 * pl.kc)));
   if (const char *e = getenv("SMP_SKETCH_SPLITS")) {   // tuning override
     const long v = strtol(e, nullptr, 10);
-    if (v >= 1) return (int)std::min<int64_t>(v, smax);
+    if (v >= 1) return (int)std::max<int64_t>(smin, std::min<int64_t>(v, smax));
   }
-  int best = 1;
+  int best = (int)smin;
   double best_cost = 1e300;
-  for (int64_t S = 1; S <= smax; ++S) {
+  for (int64_t S = smin; S <= smax; ++S) {
     const int64_t total = per * S;
     const int64_t rounds = (total + slots - 1) / slots;
     const double cost = (double)(rounds * slots) / (double)total + 2.0 * (double)S * pl.kpad / (double)d;
@@ -159,6 +167,7 @@ const char *smp_status_str(smp_status s) {
     case SMP_ERR_NUMERIC: return "numeric error";
     case SMP_ERR_CAPACITY: return "buffer capacity exceeded";
     case SMP_ERR_STATE: return "call out of order";
+    case SMP_ERR_BUSY: return "admission refused (busy)";
   }
   return "unknown status";
 }
@@ -431,7 +440,12 @@ smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const
   SMP_HIP(ctx, smp::sample_count(ws, n1, n2, p->m, p->seed, om->row_ptr, om->col_ptr, ws.cnt, ctx->stream));
   SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, om->row_ptr + n1, 8, hipMemcpyDeviceToHost, ctx->stream));
   SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned + 1, om->col_ptr + n2, 8, hipMemcpyDeviceToHost, ctx->stream));
+  SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned + 2, ws.stats + 4, 8, hipMemcpyDeviceToHost, ctx->stream));
   SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double nonfinite = 0.0;
+  std::memcpy(&nonfinite, ctx->host_pinned + 2, sizeof(double));
+  if (nonfinite != 0.0)
+    return fail(ctx, SMP_ERR_NUMERIC, "non-finite input: ||A||_F^2 or ||B||_F^2 is not finite (NaN or Inf in A or B)");
   const int64_t nnz = ctx->host_pinned[0];
   if (nnz != ctx->host_pinned[1]) return fail(ctx, SMP_ERR_DEVICE, "row and column listings disagree on |Omega|");
   om->nnz = nnz;
@@ -575,3 +589,24 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
 namespace {
 smp_ctx_bufs &bufs(smp_ctx *ctx) { return *static_cast<smp_ctx_bufs *>(ctx->ws); }
 }  // namespace
+
+namespace smp {
+
+size_t ctx_workspace_bytes(const smp_ctx *ctx) {
+  const auto *b = static_cast<const smp_ctx_bufs *>(ctx->ws);
+  size_t s = 0;
+  for (const Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm}) s += x->bytes;
+  return s;
+}
+
+void ctx_release_workspace(smp_ctx *ctx) {
+  auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
+  hipStreamSynchronize(ctx->stream);
+  for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm}) {
+    if (x->p) hipFree(x->p);
+    x->p = nullptr;
+    x->bytes = 0;
+  }
+}
+
+}  // namespace smp

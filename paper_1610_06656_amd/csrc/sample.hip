@@ -72,7 +72,7 @@ __global__ void totals_kernel(const double *__restrict__ ba, int64_t nba, const 
 // alpha_i = na2_i / den_A, beta_j = nb2_j / den_B. Every workgroup forms
 // F_A, F_B and the denominators from the block sums itself, exactly as
 // totals_kernel does (sequential over the blocks), and workgroup 0 stores them
-// in stats.
+// in stats[0..3], with stats[4] = 1 when F_A or F_B is not finite.
 __global__ void marginals_kernel(const float *__restrict__ na2, const float *__restrict__ nb2, int64_t n1,
                                  int64_t n2, const double *__restrict__ ba, int64_t nba,
                                  const double *__restrict__ bb, int64_t nbb, double *__restrict__ stats,
@@ -91,6 +91,9 @@ __global__ void marginals_kernel(const float *__restrict__ na2, const float *__r
       stats[1] = fb;
       stats[2] = da;
       stats[3] = db;
+      // a NaN or infinite entry of A or B (or a squared norm that overflows
+      // FP32) leaves a total that is not finite: flag it for the host
+      stats[4] = (__builtin_isfinite(fa) && __builtin_isfinite(fb)) ? 0.0 : 1.0;
     }
   }
   __syncthreads();

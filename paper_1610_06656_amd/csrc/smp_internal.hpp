@@ -26,6 +26,11 @@ struct smp_ctx {
 
 namespace smp {
 
+// Device bytes of library workspace a context holds now (its growable
+// buffers), and their release (after the context's stream has drained).
+size_t ctx_workspace_bytes(const smp_ctx *ctx);
+void ctx_release_workspace(smp_ctx *ctx);
+
 // ---- sketch --------------------------------------------------------------------
 struct SketchPlan {
   int prec;       // smp_precision of the MFMA operands
@@ -84,7 +89,7 @@ hipError_t pi_fill(int64_t l0, int64_t nrows, int k, uint64_t seed, float *out, 
 
 // ---- sampling ------------------------------------------------------------------
 struct SampleWs {
-  double *stats;     // [4]: F_A, F_B, den_A, den_B
+  double *stats;     // [8]: F_A, F_B, den_A, den_B, non-finite flag (1.0 when F_A or F_B is not finite)
   double *alpha;     // n1
   double *beta;      // n2
   double *blocks;    // max(n1, n2)/256 + 1

@@ -39,7 +39,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.SmpParams) == 72
     assert ctypes.sizeof(_lib.SmpOmega) == 4 * 8 + 10 * 8
     assert ctypes.sizeof(_lib.SmpJobResult) == 2 * 4 + 2 * 8
-    assert ctypes.sizeof(_lib.SmpServerStats) == 3 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(_lib.SmpServerStats) == 3 * 8 + 2 * 4 + 8 + 8
 
 
 @pytest.mark.skipif(gpu_available(), reason="checks the behaviour without a GPU")
@@ -51,6 +51,8 @@ def test_server_entry_points_without_gpu(lib):
     p = _params()
     assert lib.smp_server_submit(None, ctypes.byref(p), None, 0, None, 0, None, None, None,
                                  ctypes.byref(jid)) == _lib.SMP_ERR_INVALID_ARG
+    assert lib.smp_server_try_submit(None, ctypes.byref(p), None, 0, None, 0, None, None, None,
+                                     ctypes.byref(jid)) == _lib.SMP_ERR_INVALID_ARG
     assert lib.smp_server_wait(None, 1, None) == _lib.SMP_ERR_INVALID_ARG
     lib.smp_server_destroy(None)
     # an empty batch needs no device
@@ -92,8 +94,8 @@ def test_valid_params_and_workspace(lib):
 
 
 def test_status_strings(lib):
-    for s in range(7):
-        assert lib.smp_status_str(s)
+    for s in range(8):
+        assert lib.smp_status_str(s) and lib.smp_status_str(s) != b"unknown status"
     assert lib.smp_status_str(0) == b"ok"
 
 

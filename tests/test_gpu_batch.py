@@ -140,3 +140,73 @@ def test_solve_batch_matches_oracle(api):
         e_ora = oev.relative_error(M, ref["Uc"], ref["sigma"], ref["Vc"])
         log(f"  batch job e_gpu={e_gpu:.6e} e_oracle={e_ora:.6e}")
         assert abs(e_gpu - e_ora) <= 1e-4 * e_ora + 1e-6
+
+
+def test_non_finite_input_fails_that_job_only(api):
+    """A NaN in one job's input: smp_solve returns SMP_ERR_NUMERIC with the
+    outputs untouched, and inside a server mix that job fails with the same
+    status while every other job is bit-identical to its solve alone."""
+    jobs = [_make(api, i, j) for i, j in enumerate(JOBS[:6])]
+    bad = 2
+    jobs[bad]["A"][17, 5] = float("nan")
+    alone = _alone(api, [j for i, j in enumerate(jobs) if i != bad])
+    ctx = api.Context(0)
+    U, V, s = [torch.full_like(t, 7.0) for t in jobs[bad]["out"]]
+    with pytest.raises(api.SmpError) as e:
+        ctx.smp_solve(jobs[bad]["p"], jobs[bad]["A"], jobs[bad]["B"], U, V, s)
+    assert e.value.status == api.SMP_ERR_NUMERIC
+    assert torch.all(U == 7.0) and torch.all(V == 7.0) and torch.all(s == 7.0)
+    srv = api.Server(0, workers=3)
+    ids = [srv.submit(j["p"], j["A"], j["B"], *j["out"]) for j in jobs]
+    res = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    log(f"statuses {[r['status'] for r in res]}")
+    assert res[bad]["status"] == api.SMP_ERR_NUMERIC and "non-finite" in res[bad]["error"]
+    assert st["failed"] == 1 and st["completed"] == len(jobs)
+    others = [j for i, j in enumerate(jobs) if i != bad]
+    for j, (U, V, s) in zip(others, alone):
+        assert all(torch.equal(a, b) for a, b in zip(j["out"], (U, V, s)))
+    assert all(r["status"] == 0 for i, r in enumerate(res) if i != bad)
+
+
+def test_try_submit_refuses_while_busy(api):
+    """smp_server_try_submit answers SMP_ERR_BUSY (nothing queued) while the
+    only worker runs a job, and admits the same job once the worker is free."""
+    long_job = dict(p=api.make_params(100_000, 1024, 1024, 400, 10, T=10, seed=SEED), out=None)
+    A = torch.randn(100_000, 1024, device=DEV)
+    B = torch.randn(100_000, 1024, device=DEV)
+    outs = [torch.empty(1024, 10, dtype=torch.float64, device=DEV), torch.empty(1024, 10, dtype=torch.float64, device=DEV),
+            torch.empty(10, dtype=torch.float64, device=DEV)]
+    small = _make(api, 0, JOBS[0])
+    srv = api.Server(0, workers=1)
+    jid = srv.submit(long_job["p"], A, B, *outs)          # several ms of work on the one worker
+    assert srv.try_submit(small["p"], small["A"], small["B"], *small["out"]) is None
+    assert srv.wait(jid)["status"] == 0
+    jid2 = srv.try_submit(small["p"], small["A"], small["B"], *small["out"])
+    assert jid2 is not None and srv.wait(jid2)["status"] == 0
+    st = srv.stats()
+    srv.close()
+    assert st["refused"] == 1 and st["submitted"] == 2
+
+
+def test_budget_bounds_memory_in_use(api):
+    """With a finite budget the memory in use at every admission (retained
+    worker workspace plus the running jobs' inputs and outputs) stays within
+    it, and jobs still overlap."""
+    jobs = [_make(api, i, JOBS[8]) for i in range(8)]
+    p0 = jobs[0]["p"]
+    io = 4 * p0.d * (p0.n1 + p0.n2) + 8 * (p0.n1 + p0.n2 + 1) * p0.r
+    budget = int(2.5 * (api.smp_workspace_size(p0) + io))
+    alone = _alone(api, jobs)
+    srv = api.Server(0, workers=4, hbm_budget=budget)
+    ids = [srv.submit(j["p"], j["A"], j["B"], *j["out"]) for j in jobs]
+    res = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    log(f"budget {budget} stats {st}")
+    assert all(r["status"] == 0 for r in res)
+    assert 0 < st["max_budget_in_use"] <= budget
+    assert 2 <= st["max_running"] <= 3
+    for j, (U, V, s) in zip(jobs, alone):
+        assert torch.equal(j["out"][0], U) and torch.equal(j["out"][2], s)

@@ -369,3 +369,38 @@ def test_solve_fp8_small_and_degenerate(api, ctx, name):
     e_ora = oev.relative_error(AtB, ref["Uc"], ref["sigma"], ref["Vc"])
     log(f"  e_gpu={e_gpu:.6e} e_oracle_fp8={e_ora:.6e}")
     assert abs(e_gpu - e_ora) <= 5e-3 * e_ora + 1e-6
+
+
+def _pi_rows_e4m3(seed, k, rows_c, d):
+    """E(Z(c, l)) / sqrt(k) for selected sketch rows c and all l < d."""
+    out = np.empty((len(rows_c), d))
+    ls = np.arange(d, dtype=np.int64)
+    for t, c in enumerate(rows_c):
+        w = philox.stream_words(seed, philox.TAG_PI, ls, np.full(d, c // 4, dtype=np.int64))
+        out[t] = rounding.round_e4m3(gaussian.normals_from_words(*w)[c % 4]) / np.sqrt(k)
+    return out
+
+
+def test_c2_fp8_sketch_sampled_outputs(api, ctx):
+    """d = 200,000, n1 = n2 = 2,000, k = 400 with the FP8 pass in the
+    benchmark's launch configuration: 16 sketch rows x 24 columns of A~ and B~
+    against the oracle's FP8 definition (E4M3 Pi, E4M3 data with E8M0 scales
+    per column and 32-row block) computed one by one."""
+    c = smp_inputs.CONFIGS["c2_fp32"]
+    log("c2 fp8 sketch sampled")
+    Ad, Bd = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], SEED, device=DEV)
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], r=1, prec=api.SMP_PREC_FP8)
+    At, Bt, na2, _ = _sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"])
+    rng = np.random.default_rng(2)
+    rows_c = sorted(set(rng.choice(c["k"], 16, replace=False).tolist()) | {0, c["k"] - 1})
+    cols = sorted(set(rng.choice(c["n1"], 24, replace=False).tolist()) | {0, c["n1"] - 1})
+    P = _pi_rows_e4m3(p.seed, c["k"], rows_c, c["d"])
+    for X, S in ((Ad, At), (Bd, Bt)):
+        Xs = rounding.quantize_e4m3_blocks(X[:, cols].double().cpu().numpy())
+        ref = P @ Xs
+        got = S[cols][:, rows_c].astype(np.float64).T
+        col_rel = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        log(f"  max column rel {col_rel.max():.3e}")
+        assert col_rel.max() < TOL_FP8
+    ref_na2 = (Ad.double() ** 2).sum(0).cpu().numpy()
+    assert np.allclose(na2, ref_na2, rtol=1e-6)

@@ -310,3 +310,43 @@ def _waltmin_parity(api, ctx, name):
     assert np.all(np.diff(sg) <= 1e-12 * sg[0])
     _, s_ref, _ = owm.canonical(ref["U"], ref["V"])
     assert np.allclose(sg, s_ref, rtol=1e-6)
+
+
+@pytest.mark.parametrize("T", [0, 3])
+def test_waltmin_trim_fires_like_the_oracle(api, ctx, T):
+    """Alg. 2 step 6 on a crafted case where it fires: one spike M~_00
+    dominates R, but ||A_0|| is tiny, so ||U0_0|| exceeds
+    8 sqrt(r) ||A_0|| / ||A||_F and row 0 of U0 is zeroed. The GPU's trimmed
+    initial factors (T = 0) and the iterates from them (T = 3) match the
+    oracle's product, and row 0 of the T = 0 output is zero."""
+    n1 = n2 = 20
+    r = 2
+    M = np.zeros((n1, n2))
+    M[0, 0] = 100.0
+    M[1:, 1:] = np.random.default_rng(0).standard_normal((19, 19)) * 0.01
+    rows, cols = [a.ravel() for a in np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")]
+    w = np.ones(rows.size)
+    na32 = np.ones(n1, dtype=np.float32)
+    na32[0] = 1e-6
+    ref = owm.waltmin(n1, n2, rows, cols, w, M.ravel(), r, T, na32.astype(np.float64), fixed_FA(na32))
+    assert ref["trimmed"][0] and ref["trimmed"].sum() == 1
+    X_ref = ref["U"] @ ref["V"].T
+
+    class Om:   # the oracle's fully observed grid in the form omega_from_oracle takes
+        pass
+    om = Om()
+    om.nnz, om.rows, om.cols, om.w, om.subset = rows.size, rows, cols, w, None
+    o, _ = omega_from_oracle(om, n1, n2, mt=M.ravel())
+    p = api.make_params(1000, n1, n2, 8, r, T=T, m=1e6, init_iters=40)
+    U = torch.empty(n1, r, dtype=torch.float64, device=DEV)
+    V = torch.empty(n2, r, dtype=torch.float64, device=DEV)
+    s = torch.empty(r, dtype=torch.float64, device=DEV)
+    ctx.smp_waltmin(p, o, torch.from_numpy(na32).to(DEV), U, V, s)
+    torch.cuda.synchronize()
+    X = product(U.cpu().numpy(), s.cpu().numpy(), V.cpu().numpy())
+    rel = np.linalg.norm(X - X_ref) / np.linalg.norm(X_ref)
+    log(f"  trim T={T}: rel diff {rel:.3e}, |X[0,:]| max {np.abs(X[0]).max():.3e}")
+    assert rel < 1e-6
+    if T == 0:
+        assert np.all(X[0] == 0.0)
+        assert abs(X[0, 0]) < 1.0 < abs(M[0, 0])      # the spike is gone

@@ -153,6 +153,23 @@ def test_optimal_error_is_eckart_young():
     assert abs(e - s[r] / s[0]) < 1e-12
 
 
+def test_product_is_exact_over_many_chunks():
+    """A^T B accumulated over several 16,384-row chunks with a ragged last
+    chunk: on small-integer data every FP64 partial sum is an exact integer,
+    so the result must equal the exact integer product (int64 arithmetic),
+    for A^T B and for the A = B path."""
+    rng = np.random.default_rng(12)
+    d = 3 * 16384 + 517
+    A = rng.integers(-8, 9, size=(d, 30)).astype(np.float32)
+    B = rng.integers(-8, 9, size=(d, 23)).astype(np.float32)
+    Ai, Bi = A.astype(np.int64), B.astype(np.int64)
+    got = evaluate.product(A, B)
+    assert np.array_equal(got, (Ai.T @ Bi).astype(np.float64))
+    assert np.array_equal(evaluate.product(A, None), (Ai.T @ Ai).astype(np.float64))
+    # dropping or repeating any chunk changes the exact result
+    assert not np.array_equal(got, (Ai[16384:].T @ Bi[16384:]).astype(np.float64))
+
+
 def test_spectral_norm_large_path_matches_lapack():
     M = np.random.default_rng(1).standard_normal((1600, 1501))
     import scipy.linalg
