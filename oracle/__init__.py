@@ -13,6 +13,7 @@ Module map (each function cites the passage of the paper it follows):
 * ``gaussian``  Box-Muller transform of two 24-bit uniforms
 * ``sketch``    Alg. 1 step 2 / Section 2 "Step 1": Pi, sketches, column norms
 * ``sample``    Eq. (1) and Alg. 1 step 3: q, q-hat, Omega, weights
+* ``multinomial`` Appendix D "Sampling": row-wise multinomial draws of Omega
 * ``estimate``  Eq. (2): rescaled-JL estimates on Omega
 * ``waltmin``   Appendix A, Alg. 2: WAltMin init, trim, alternating solves
 * ``evaluate``  Section 4 "spectral norm error" and the best rank-r error
@@ -22,4 +23,4 @@ Parity status: every function is pinned by a ``-m "not gpu"`` test except
 those marked "parity unpinned" in their docstring.
 """
 
-from . import philox, gaussian, sketch, sample, estimate, waltmin, evaluate, solve  # noqa: F401
+from . import philox, gaussian, sketch, sample, multinomial, estimate, waltmin, evaluate, solve  # noqa: F401

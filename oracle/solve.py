@@ -9,6 +9,7 @@ import numpy as np
 
 from . import sketch as _sketch
 from . import sample as _sample
+from . import multinomial as _multinomial
 from . import estimate as _estimate
 from . import waltmin as _waltmin
 
@@ -20,10 +21,12 @@ def default_m(n1, n2, r):
     return 4.0 * n * r * math.log(n)
 
 
-def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None):
+def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None, sampler="binomial"):
     """Run Alg. 1. A: d x n1, B: d x n2 or None (A = B, Section 3 Remark 3).
     sketch_fmt: None for the FP64 pass, or a narrow format ("bf16", "fp8") whose
     rounded operands form the sketches (``oracle.sketch.sketch_lowp``).
+    sampler: "binomial" (Alg. 1 step 3, ``oracle.sample``) or "multinomial"
+    (the row-wise sampler of Appendix D, ``oracle.multinomial``).
     Returns a dict with the output factors and every intermediate:
       At, Bt, na2, nb2      sketches and squared column norms (step 2)
       omega                  oracle.sample.Omega (step 3)
@@ -35,7 +38,12 @@ def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None):
         At, Bt, na2, nb2 = _sketch.sketch(A, B, seed, k)
     else:
         At, Bt, na2, nb2 = _sketch.sketch_lowp(A, B, seed, k, sketch_fmt)
-    om = _sample.sample(na2, nb2, m, seed, T=T, split=split)
+    if sampler == "multinomial":
+        om = _multinomial.sample(na2, nb2, m, seed, T=T, split=split)
+    elif sampler == "binomial":
+        om = _sample.sample(na2, nb2, m, seed, T=T, split=split)
+    else:
+        raise ValueError(f"unknown sampler {sampler!r}")
     mt = _estimate.estimate(At, Bt, na2, nb2, om.rows, om.cols)
     res = _waltmin.waltmin(om.n1, om.n2, om.rows, om.cols, om.w, mt, r, T, na2, om.FA,
                            subset=om.subset)
