@@ -81,7 +81,10 @@ typedef enum smp_omega_mode {
   SMP_OMEGA_SPLIT = 1       /* Alg. 2 step 3: 2T+1 random subsets, one per step */
 } smp_omega_mode;
 
-enum { SMP_B_IS_A = 1u };   /* flags: B is A (PCA of A^T A, Section 3 Remark 3) */
+enum {
+  SMP_B_IS_A = 1u,              /* flags: B is A (PCA of A^T A, Section 3 Remark 3) */
+  SMP_SAMPLE_MULTINOMIAL = 2u   /* flags: draw Omega row by row (Appendix D) instead of one coin per entry */
+};
 
 /* The problem statement of Section 2 (A, B, r, k, m, T) plus the seed. */
 typedef struct smp_params {
@@ -91,7 +94,7 @@ typedef struct smp_params {
   int32_t T;          /* WAltMin iterations; 0 <= T <= 1000 */
   int32_t prec;       /* smp_precision of the sketch GEMM */
   int32_t omega_mode; /* smp_omega_mode */
-  uint32_t flags;     /* SMP_B_IS_A */
+  uint32_t flags;     /* SMP_B_IS_A | SMP_SAMPLE_MULTINOMIAL */
   double m;           /* sample-count parameter of Eq. (1); > 0 */
   uint64_t seed;      /* Philox key */
   int32_t init_iters; /* subspace iterations of the WAltMin init; 0 = default (2) */
@@ -140,8 +143,13 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes);
 
 /* ---- a1: the sketching matrix Pi (Alg. 1 step 2) ----------------------------
  * Writes rows l0 .. l0+nrows-1 of Pi^T: out[(l-l0)*k + c] = Pi(c, l) (FP32,
- * N(0,1/k), the same values the sketch pass uses). For inspection and tests;
- * the sketch pass itself never stores Pi. */
+ * N(0,1/k), the same values the sketch pass uses). For inspection and tests.
+ * The sketch pass never holds all of Pi: the FP32 pass regenerates each
+ * block of Pi inside the workgroup that multiplies it; the BF16 and FP8
+ * passes draw Pi (already rounded, in the matrix-core operand order) one
+ * window of data rows at a time into library scratch of at most 64 MiB
+ * (smp_workspace_size does not grow with d through Pi) and multiply that
+ * window before drawing the next. */
 smp_status smp_pi_fill(smp_ctx *ctx, const smp_params *p, int64_t l0, int64_t nrows, float *out);
 
 /* ---- a2+a3: the single pass (Alg. 1 step 2; Section 2 "Step 1") -------------
@@ -174,7 +182,17 @@ void smp_sketch_free(smp_sketch_state *st);
  * cap, returns SMP_ERR_CAPACITY with om->nnz = |Omega| and no entries written.
  * If ||A||_F^2 or ||B||_F^2 (the sums of na2, nb2) is not finite - a NaN or
  * Inf in A or B, or a squared norm beyond the FP32 range - returns
- * SMP_ERR_NUMERIC and writes no entries. */
+ * SMP_ERR_NUMERIC and writes no entries.
+ *
+ * With SMP_SAMPLE_MULTINOMIAL in p->flags, Omega is drawn row by row instead
+ * (Appendix D, "Sampling"): row i makes c_i draws with replacement, c_i the
+ * randomised rounding of m_i = m (||A_i||^2/(2||A||_F^2) + 1/(2 n1)), each
+ * from q_ij / m_i by binary search over an integer CDF (52-bit fixed-point
+ * weights a_i = floor(alpha_i 2^52), b_j = floor(beta_j 2^52) of the same
+ * binary64 marginals; CDF_i(j) = (j+1) a_i + b_0 + ... + b_j). An entry drawn
+ * N_ij times is listed once with w = N_ij / q_ij, q_ij = m (a_i + b_j) 2^-52.
+ * O(n1 + n2 + m log(n1 n2)) work instead of O(n1 n2); the sort of the draws
+ * is deterministic, so Omega is the same on every run. |Omega| <= m + n1 + 16. */
 smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const float *nb2, smp_omega *om);
 
 /* ---- a3 (rescale) + a5: estimates on Omega (Eq. (2)) -------------------------
@@ -188,9 +206,10 @@ smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, cons
  * Init: top-r left/right singular subspace of R = w .* P_Omega0(M~) by block
  * subspace iteration; rows of U0 with ||U0_i|| > 8 sqrt(r) sqrt(na2_i / F_A)
  * are zeroed (trim). T alternating steps: V_j = argmin sum_i w_ij (q_i^T v - M~_ij)^2
- * with q the rows of U, then the same for U against V (Alg. 2 orthonormalises
- * the fixed factor first; that changes only the basis of the solution, not
- * U V^T, so it is done once, on V before the last step); every r x r system
+ * with q the rows of U, then the same for U against V. The fixed factor is
+ * used as it is; orthonormalising it first would change only the basis of
+ * the solution, not U V^T (when the fixed factor has full rank r), so V is
+ * orthonormalised once, before the last step; every r x r system
  * is solved by FP64 Cholesky (pivot <= 1e-12 max diag:
  * retry on G + 1e-9 tr(G)/r I; else 0). Output in canonical form
  * U V^T -> U diag(sigma) V^T with U (n1 x r), V (n2 x r) orthonormal and

@@ -55,7 +55,9 @@ std::string check(const smp_params *p) {
   if (p->omega_mode != SMP_OMEGA_REUSE && p->omega_mode != SMP_OMEGA_SPLIT) return "unknown omega_mode";
   if (p->init_iters < 0 || p->init_iters > 1000) return "init_iters must be in [0, 1000]";
   if (p->reserved != 0) return "reserved must be 0";
+  if (p->flags & ~(uint32_t)(SMP_B_IS_A | SMP_SAMPLE_MULTINOMIAL)) return "unknown flags";
   if ((p->flags & SMP_B_IS_A) && p->n1 != p->n2) return "SMP_B_IS_A needs n1 == n2";
+  if ((p->flags & SMP_SAMPLE_MULTINOMIAL) && p->m > 1e12) return "m too large for the multinomial sampler";
   if ((p->n1 + 1) * 4 > INT32_MAX || p->n2 > INT32_MAX / 4) return "n1, n2 too large for int32 entry indices";
   return "";
 }
@@ -66,20 +68,24 @@ std::string check(const smp_params *p) {
 // near 4e-6, below the 1e-5 per-column bound, whatever d is.
 constexpr int64_t kFp32RowsPerSplit = 32768;
 
-// Number of d-splits S of the sketch pass. The kt * tiles * S workgroups run
-// in ceil(total / slots) rounds on the slots the device holds at once; the
-// S partial sketches are written once and read once by the reduction. S
-// minimises (streaming time with the last round's idle slots) + (partial
-// traffic), both relative to one perfectly balanced read of the input:
-//   cost(S) = rounds * slots / total + 2 S kpad / d,
+// Number of d-splits S of the sketch pass. The kt * tiles * S workgroups of a
+// launch run in ceil(total / slots) rounds on the slots the device holds at
+// once; each launch writes (and, after the first, reads back) the S partial
+// sketches, and the reduction reads them once. A stored-Pi pass makes one
+// launch per Pi window of w = pi_window_rows rows, the other passes one launch
+// over all d rows (w = d). S minimises (streaming time with the last round's
+// idle slots) + (partial traffic), both relative to one perfectly balanced
+// read of the input:
+//   cost(S) = rounds * slots / total + 2 S kpad / w,
 // with at least 256 rows per split and, for the FP32 pass, at most
 // kFp32RowsPerSplit.
 int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
   const int64_t tiles = (n1 + pl.ncol_tile - 1) / pl.ncol_tile + (n2 + pl.ncol_tile - 1) / pl.ncol_tile;
   const int64_t per = (int64_t)pl.kt * tiles;
   const int64_t slots = smp::sketch_slots(pl);
+  const int64_t wrows = pl.pi_stored ? std::min<int64_t>(d, smp::pi_window_rows(pl)) : d;
   const int64_t smin = pl.prec == SMP_PREC_FP32 ? (d + kFp32RowsPerSplit - 1) / kFp32RowsPerSplit : 1;
-  const int64_t smax = std::max<int64_t>(smin, std::min<int64_t>(256, d / std::max(256, 2 * pl.kc)));
+  const int64_t smax = std::max<int64_t>(smin, std::min<int64_t>(256, wrows / std::max(256, 2 * pl.kc)));
   if (const char *e = getenv("SMP_SKETCH_SPLITS")) {   // tuning override
     const long v = strtol(e, nullptr, 10);
     if (v >= 1) return (int)std::max<int64_t>(smin, std::min<int64_t>(v, smax));
@@ -89,7 +95,7 @@ int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
   for (int64_t S = smin; S <= smax; ++S) {
     const int64_t total = per * S;
     const int64_t rounds = (total + slots - 1) / slots;
-    const double cost = (double)(rounds * slots) / (double)total + 2.0 * (double)S * pl.kpad / (double)d;
+    const double cost = (double)(rounds * slots) / (double)total + 2.0 * (double)S * pl.kpad / (double)wrows;
     if (cost < best_cost - 1e-12) {
       best_cost = cost;
       best = (int)S;
@@ -149,7 +155,7 @@ struct smp_sketch_state {
 };
 
 struct smp_ctx_bufs {
-  Buf sketch, samplews, head, omega, est, wm;
+  Buf sketch, samplews, head, omega, est, wm, mn;
 };
 
 namespace {
@@ -205,7 +211,7 @@ void smp_destroy(smp_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
   if (b) {
-    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm})
+    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn})
       if (x->p) hipFree(x->p);
     delete b;
   }
@@ -253,10 +259,14 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes) {
   size_t s = 0;
   const int slots = smp::sketch_slots_total(pl, S);
   s += al((size_t)slots * nt * pl.kpad * 4) + al((size_t)slots * nt * 8);   // sketch partials
-  s += al(smp::sketch_pi_bytes(pl, p->d));                                  // stored Pi of the one-shot pass
+  s += al(smp::sketch_pi_bytes(pl, p->d));                                  // stored-Pi window of the one-shot pass
   s += al(nt * k * 4) + al(nt * 4);                                       // sketches + norms
   s += al(64) + al(nt * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);   // sampling
-  const double nnz = std::min<double>((double)p->n1 * (double)p->n2, p->m + 6.0 * std::sqrt(p->m) + 64.0);
+  const bool multi = (p->flags & SMP_SAMPLE_MULTINOMIAL) != 0;
+  if (multi) s += al(smp::mn_ws_bytes(p->n1, p->n2, p->m));               // multinomial draws and sorts
+  const double nnz = std::min<double>((double)p->n1 * (double)p->n2,
+                                      multi ? (double)smp::mn_draw_bound(p->n1, p->m)
+                                            : p->m + 6.0 * std::sqrt(p->m) + 64.0);
   s += 2 * al((size_t)(p->n1 + p->n2 + 2) * 8) + (size_t)(nnz * (4 + 8 + 8 + 1) * 2) + 8 * 256;  // omega
   s += 2 * al(nt * 8);                                                    // estimate
   s += smp::waltmin_ws_bytes(p->n1, p->n2, p->r, (int64_t)nnz);
@@ -421,6 +431,27 @@ static smp_status sample_ws(smp_ctx *ctx, int64_t n1, int64_t n2, smp::SampleWs 
   return SMP_OK;
 }
 
+// The multinomial sampler's scratch in the context's buffer (carved the same
+// way on every call, like sample_ws).
+static smp_status mn_ws(smp_ctx *ctx, int64_t n1, int64_t n2, double m, smp::MnWs &w) {
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.mn, smp::mn_ws_bytes(n1, n2, m));
+  if (s != SMP_OK) return s;
+  smp::mn_ws_carve(b.mn.p, n1, n2, m, w);
+  return SMP_OK;
+}
+
+// The fill pass of the sampler selected by p->flags, after its count pass.
+static hipError_t sample_fill_any(smp_ctx *ctx, const smp_params *p, const smp::SampleWs &ws, const smp_omega &om) {
+  const int split = p->omega_mode == SMP_OMEGA_SPLIT ? 1 : 0;
+  if (p->flags & SMP_SAMPLE_MULTINOMIAL) {
+    smp::MnWs mws;
+    smp::mn_ws_carve(bufs(ctx).mn.p, p->n1, p->n2, p->m, mws);
+    return smp::mn_fill(ws, mws, p->n1, p->n2, p->m, p->seed, p->T, split, om, ctx->stream);
+  }
+  return smp::sample_fill(ws, p->n1, p->n2, p->m, p->seed, p->T, split, om, ctx->stream);
+}
+
 smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const float *nb2, smp_omega *om) {
   if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
   const std::string m = check(p);
@@ -433,13 +464,21 @@ smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const
   if (split && om->cap > 0 && (!om->sub_csr || !om->sub_csc))
     return fail(ctx, SMP_ERR_INVALID_ARG, "SPLIT mode needs sub_csr and sub_csc");
   const int64_t n1 = p->n1, n2 = p->n2;
+  const bool multi = (p->flags & SMP_SAMPLE_MULTINOMIAL) != 0;
   smp::SampleWs ws;
   smp_status s = sample_ws(ctx, n1, n2, ws);
   if (s != SMP_OK) return s;
+  smp::MnWs mws;
+  if (multi && (s = mn_ws(ctx, n1, n2, p->m, mws)) != SMP_OK) return s;
   SMP_HIP(ctx, smp::sample_prepare(na2, nb2, n1, n2, ws, ctx->stream));
-  SMP_HIP(ctx, smp::sample_count(ws, n1, n2, p->m, p->seed, om->row_ptr, om->col_ptr, ws.cnt, ctx->stream));
+  if (multi) {
+    SMP_HIP(ctx, smp::mn_count(ws, mws, n1, n2, p->m, p->seed, om->row_ptr, ctx->stream));
+    SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned + 1, mws.doff + n1, 8, hipMemcpyDeviceToHost, ctx->stream));
+  } else {
+    SMP_HIP(ctx, smp::sample_count(ws, n1, n2, p->m, p->seed, om->row_ptr, om->col_ptr, ws.cnt, ctx->stream));
+    SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned + 1, om->col_ptr + n2, 8, hipMemcpyDeviceToHost, ctx->stream));
+  }
   SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, om->row_ptr + n1, 8, hipMemcpyDeviceToHost, ctx->stream));
-  SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned + 1, om->col_ptr + n2, 8, hipMemcpyDeviceToHost, ctx->stream));
   SMP_HIP(ctx, hipMemcpyAsync(ctx->host_pinned + 2, ws.stats + 4, 8, hipMemcpyDeviceToHost, ctx->stream));
   SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   double nonfinite = 0.0;
@@ -447,11 +486,16 @@ smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const
   if (nonfinite != 0.0)
     return fail(ctx, SMP_ERR_NUMERIC, "non-finite input: ||A||_F^2 or ||B||_F^2 is not finite (NaN or Inf in A or B)");
   const int64_t nnz = ctx->host_pinned[0];
-  if (nnz != ctx->host_pinned[1]) return fail(ctx, SMP_ERR_DEVICE, "row and column listings disagree on |Omega|");
+  if (multi) {
+    if (ctx->host_pinned[1] > mws.dmax || nnz > ctx->host_pinned[1])
+      return fail(ctx, SMP_ERR_DEVICE, "multinomial draws exceed their bound");
+  } else if (nnz != ctx->host_pinned[1]) {
+    return fail(ctx, SMP_ERR_DEVICE, "row and column listings disagree on |Omega|");
+  }
   om->nnz = nnz;
   if (nnz > om->cap)
     return fail(ctx, SMP_ERR_CAPACITY, "|Omega| = " + std::to_string(nnz) + " exceeds cap " + std::to_string(om->cap));
-  SMP_HIP(ctx, smp::sample_fill(ws, n1, n2, p->m, p->seed, p->T, split ? 1 : 0, *om, ctx->stream));
+  SMP_HIP(ctx, sample_fill_any(ctx, p, ws, *om));
   return SMP_OK;
 }
 
@@ -564,7 +608,7 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
     smp::SampleWs ws;
     s = sample_ws(ctx, n1, n2, ws);
     if (s != SMP_OK) return s;
-    SMP_HIP(ctx, smp::sample_fill(ws, n1, n2, q.m, q.seed, q.T, split ? 1 : 0, om, ctx->stream));
+    SMP_HIP(ctx, sample_fill_any(ctx, &q, ws, om));
   }
   mark(ctx, kStSample, true);
   mark(ctx, kStEstimate, false);
@@ -595,14 +639,14 @@ namespace smp {
 size_t ctx_workspace_bytes(const smp_ctx *ctx) {
   const auto *b = static_cast<const smp_ctx_bufs *>(ctx->ws);
   size_t s = 0;
-  for (const Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm}) s += x->bytes;
+  for (const Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn}) s += x->bytes;
   return s;
 }
 
 void ctx_release_workspace(smp_ctx *ctx) {
   auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
   hipStreamSynchronize(ctx->stream);
-  for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm}) {
+  for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn}) {
     if (x->p) hipFree(x->p);
     x->p = nullptr;
     x->bytes = 0;

@@ -315,13 +315,11 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   g.seed = seed;
   g.part = part;
   g.npart = npart;
+  // stored Pi: pi_buf holds the Pi fragments of the launch's own rows (one window)
   auto launch = [&](KernelPtr kern, int64_t r0, int64_t nrows, int splits, int64_t rps, int s_base, int extra = 0,
                     int unit = 0) {
     g.row0 = r0;
-    // stored Pi: the launch's first row r0 is a whole number of 32-row blocks past row0
-    g.pi = pl.pi_stored ? static_cast<const char *>(pi_buf) +
-                              (size_t)((r0 - row0) / pl.pi_rows) * pl.mt_total * pl.pi_frag_bytes
-                        : nullptr;
+    g.pi = pl.pi_stored ? pi_buf : nullptr;
     g.rows = nrows;
     g.S = splits;
     g.rows_per_split = rps;
@@ -348,29 +346,42 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
     return launch(kern, row0, rows, S, rps, 0);
   }
 
-  // BF16 / FP8: a main launch over S splits holding every whole Pi block (the
+  // BF16 / FP8: main launches over S splits holding every whole block (the
   // first nblk mod S splits one block more than the others), and a tail launch
   // (one split, clamped) for the rows past the last whole block, into partial
   // slot S. The tail launch also runs with no rows, so that a one-shot pass
   // stores zeros in that slot.
-  if (pl.pi_stored) {
-    const hipError_t e = pi_store(pl, seed, row0, rows, k, pi_buf, st);
-    if (e != hipSuccess) return e;
-  }
+  //
+  // Stored Pi is drawn one window of at most pi_window_rows(pl) rows at a
+  // time, just before the launch that reads it: the whole blocks are cut into
+  // nwin windows of equal size (the first nblk mod nwin one block longer),
+  // each one Pi draw plus one main launch; the first window's launch stores
+  // the partials of a one-shot pass, every later one adds into them.
   const bool vec = g.a.vec_ok && g.b.vec_ok;
   KernelPtr kmain = reinterpret_cast<KernelPtr>(vec ? pl.kernel : pl.kernel_scalar);
   KernelPtr ktail = reinterpret_cast<KernelPtr>(vec ? pl.kernel_clamp : pl.kernel_scalar);
   if (!kmain || !ktail) return hipErrorInvalidValue;
   const int64_t nblk = rows / pl.kc;
-  const int64_t rps = nblk / S * pl.kc;
-  const int extra = (int)(nblk % S);
   const int64_t main_rows = nblk * pl.kc;
-  if (main_rows > 0 || !accumulate) {   // with no whole block the one-shot pass still stores zero partials
-    const hipError_t e = launch(kmain, row0, main_rows, S, rps, 0, extra, pl.kc);
-    if (e != hipSuccess) return e;
+  const int64_t wblk = pl.pi_stored ? pi_window_rows(pl) / pl.kc : nblk;
+  const int64_t nwin = nblk == 0 ? 0 : (nblk + wblk - 1) / wblk;
+  hipError_t e = hipSuccess;
+  if (nblk == 0 && !accumulate) {   // with no whole block the one-shot pass still stores zero partials
+    if ((e = launch(kmain, row0, 0, S, 0, 0, 0, pl.kc)) != hipSuccess) return e;
+  }
+  for (int64_t w = 0; w < nwin; ++w) {
+    const int64_t wb0 = w * (nblk / nwin) + std::min<int64_t>(w, nblk % nwin);
+    const int64_t wbn = nblk / nwin + (w < nblk % nwin ? 1 : 0);
+    const int64_t r0 = row0 + wb0 * pl.kc;
+    if (pl.pi_stored && (e = pi_store(pl, seed, r0, wbn * pl.kc, k, pi_buf, st)) != hipSuccess) return e;
+    g.accumulate = (accumulate || w > 0) ? 1 : 0;
+    if ((e = launch(kmain, r0, wbn * pl.kc, S, wbn / S * pl.kc, 0, (int)(wbn % S), pl.kc)) != hipSuccess) return e;
   }
   const int64_t tail = rows - main_rows;
   if (tail == 0 && accumulate) return hipSuccess;
+  if (pl.pi_stored && tail > 0 && (e = pi_store(pl, seed, row0 + main_rows, tail, k, pi_buf, st)) != hipSuccess)
+    return e;
+  g.accumulate = accumulate ? 1 : 0;
   return launch(ktail, row0 + main_rows, tail, 1, (tail + pl.kc - 1) / pl.kc * pl.kc, S);
 }
 
@@ -384,9 +395,25 @@ hipError_t sketch_finish(const SketchPlan &pl, const float *part, const double *
   return hipGetLastError();
 }
 
+// Bytes of Pi fragments per data row of a stored-Pi pass (BF16: 32 B per
+// m-tile, FP8: 16 B per m-tile).
+static int64_t pi_row_bytes(const SketchPlan &pl) { return (int64_t)pl.mt_total * pl.pi_frag_bytes / pl.pi_rows; }
+
+int64_t pi_window_rows(const SketchPlan &pl) {
+  if (!pl.pi_stored) return 0;
+  int64_t cap = kPiWindowBytes;
+  if (const char *e = getenv("SMP_PI_WINDOW_MB")) {   // tuning override
+    const long v = strtol(e, nullptr, 10);
+    if (v >= 1 && v <= 4096) cap = (int64_t)v << 20;
+  }
+  const int64_t rows = cap / pi_row_bytes(pl) / pl.kc * pl.kc;
+  return std::max<int64_t>(rows, pl.kc);
+}
+
 size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows) {
   if (!pl.pi_stored || rows <= 0) return 0;
-  return (size_t)((rows + pl.pi_rows - 1) / pl.pi_rows) * (size_t)pl.mt_total * (size_t)pl.pi_frag_bytes;
+  const int64_t wr = std::min<int64_t>((rows + pl.pi_rows - 1) / pl.pi_rows * pl.pi_rows, pi_window_rows(pl));
+  return (size_t)(wr / pl.pi_rows) * (size_t)pl.mt_total * (size_t)pl.pi_frag_bytes;
 }
 
 hipError_t pi_store(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,

@@ -45,7 +45,7 @@ struct SketchPlan {
   void *kernel;         // the instantiated kernel for this shape
   void *kernel_clamp;   // BF16, FP8: variant for partial blocks (the tail launch), else null
   void *kernel_scalar;  // BF16, FP8: variant with guarded scalar loads (unaligned or ragged inputs), else null
-  int pi_stored;        // 1: Pi is drawn once per push into a buffer that the pass streams
+  int pi_stored;        // 1: Pi is drawn window by window into a buffer that the pass streams
   int pi_rows;          // stored Pi: data rows per fragment block (32 BF16, 128 FP8)
   int pi_frag_bytes;    // stored Pi: bytes of one fragment (one MFMA A operand: 1024 BF16, 2048 FP8)
 };
@@ -59,8 +59,15 @@ SketchPlan sketch_plan(int k, int prec);
 SketchPlan sketch_plan_bf16(int k);
 SketchPlan sketch_plan_fp8(int k);
 
+// Stored-Pi passes draw Pi one window at a time into a buffer of at most
+// kPiWindowBytes (the window: pi_window_rows(pl) data rows, a whole number of
+// blocks), so the buffer does not grow with d.
+constexpr int64_t kPiWindowBytes = 64ll << 20;
+int64_t pi_window_rows(const SketchPlan &pl);
+
 // Bytes of the stored-Pi buffer a push of `rows` rows needs (0 unless
-// pl.pi_stored), and the kernel that fills it for rows [r0, r0 + rows).
+// pl.pi_stored; at most one window), and the kernel that fills it for rows
+// [r0, r0 + rows).
 size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows);
 hipError_t pi_store(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf, hipStream_t st);
 hipError_t pi_store_bf16(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
@@ -72,11 +79,12 @@ hipError_t pi_store_fp8(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t
 // (CUs x resident workgroups per CU).
 int sketch_slots(const SketchPlan &pl);
 
+
 // Pass over rows [row0, row0+rows) of A (and B). part: [S][n1+n2][kpad] FP32,
 // npart: [S][n1+n2] FP64. accumulate: add into the partials (zeroed by the
 // caller before the first push); otherwise store them (a single push covering
 // all rows). pi_buf: sketch_pi_bytes(pl, rows) bytes of scratch (may be null
-// when that is 0).
+// when that is 0); the pass draws Pi into it window by window.
 hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
                        int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, bool accumulate,
                        float *part, double *npart, void *pi_buf, hipStream_t st);
@@ -101,6 +109,29 @@ hipError_t sample_count(const SampleWs &ws, int64_t n1, int64_t n2, double m, ui
                         int64_t *col_ptr, int64_t *scan_tmp, hipStream_t st);
 hipError_t sample_fill(const SampleWs &ws, int64_t n1, int64_t n2, double m, uint64_t seed, int T, int split,
                        const smp_omega &om, hipStream_t st);
+
+// Row-wise multinomial sampler (Appendix D): device scratch and the two
+// passes (count: draws, sort, distinct entries per row -> row_ptr; fill: the
+// CSR entries, then the CSC listing).
+struct MnWs {
+  int64_t dmax = 0;     // bound on the number of draws (buffers' size)
+  int64_t ntiles = 0;   // radix-sort tiles of dmax keys
+  uint64_t *a = nullptr, *tot = nullptr;          // n1 each
+  int64_t *cnt = nullptr, *dcnt = nullptr;        // n1 each
+  int64_t *doff = nullptr;                        // n1 + 1
+  int64_t *b = nullptr;                           // n2
+  int64_t *bptr = nullptr;                        // n2 + 1
+  uint64_t *keys0 = nullptr, *keys1 = nullptr;    // dmax each
+  int64_t *hist = nullptr, *hoff = nullptr;       // 256 ntiles, + 1
+  int64_t *csum = nullptr, *coff = nullptr;       // scan chunk sums / offsets
+};
+int64_t mn_draw_bound(int64_t n1, double m);
+size_t mn_ws_bytes(int64_t n1, int64_t n2, double m);
+void mn_ws_carve(void *base, int64_t n1, int64_t n2, double m, MnWs &w);
+hipError_t mn_count(const SampleWs &ws, const MnWs &w, int64_t n1, int64_t n2, double m, uint64_t seed,
+                    int64_t *row_ptr, hipStream_t st);
+hipError_t mn_fill(const SampleWs &ws, const MnWs &w, int64_t n1, int64_t n2, double m, uint64_t seed, int T,
+                   int split, const smp_omega &om, hipStream_t st);
 
 // ---- estimate ------------------------------------------------------------------
 // na/nb: sketch-column norms, sa/sb: data-column norms (FP64 scratch, n1 / n2)

@@ -93,6 +93,23 @@ def test_valid_params_and_workspace(lib):
     assert size.value > 4000 * 400 * 4
 
 
+@pytest.mark.parametrize("prec", [1, 2])
+def test_workspace_does_not_grow_with_d_through_pi(lib, prec):
+    """Alg. 1 step 2 draws Pi, the pass does not keep it: the stored-Pi BF16
+    and FP8 passes hold at most two bounded windows of Pi (64 MiB each), so
+    from d = 10^6 to d = 10^7 the workspace grows only by what depends on d
+    through the split-K partials and nothing else (it is the same here)."""
+    size = ctypes.c_size_t(0)
+    sizes = []
+    for d in (1_000_000, 4_000_000, 10_000_000):
+        p = _params(d=d, n1=4096, n2=4096, k=1024, r=20, prec=prec)
+        assert lib.smp_workspace_size(ctypes.byref(p), ctypes.byref(size)) == _lib.SMP_OK
+        sizes.append(size.value)
+    assert sizes[0] == sizes[1] == sizes[2]
+    # a full k x d Pi at d = 10^7 would be 20 GB (BF16) / 10 GB (FP8) alone
+    assert sizes[2] < 2_000_000_000
+
+
 def test_status_strings(lib):
     for s in range(8):
         assert lib.smp_status_str(s) and lib.smp_status_str(s) != b"unknown status"

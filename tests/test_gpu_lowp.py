@@ -159,6 +159,57 @@ def test_sketch_bf16_streaming_push_any_order(api, ctx):
     assert np.allclose(na2.cpu().numpy(), ona2, rtol=1e-6)
 
 
+@pytest.mark.parametrize("prec_name", ["bf16", "fp8"])
+@pytest.mark.parametrize("name", ["k400_tiles", "ragged"])
+def test_sketch_pi_windows(api, ctx, name, prec_name, monkeypatch):
+    """The stored-Pi passes draw Pi one bounded window at a time (Alg. 1
+    step 2: Pi is drawn, not kept). With a 1 MiB window the k = 400 case runs
+    16 BF16 / 8 FP8 windows (the ragged one a single window and a tail); each
+    window's launch adds into the partials of the ones before. The result
+    meets the oracle's bar and differs from the one-window pass only by the
+    FP32 rounding of those additions."""
+    c = SKETCH_CASES[name] if prec_name == "bf16" else FP8_CASES[name]
+    prec = api.SMP_PREC_BF16 if prec_name == "bf16" else api.SMP_PREC_FP8
+    tol = TOL_SKETCH if prec_name == "bf16" else TOL_FP8
+    log(f"{prec_name} windowed sketch {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=min(5, c["n1"], c["n2"]))
+    oAt, oBt, ona2, onb2 = osk.sketch_lowp(A.numpy(), B.numpy(), SEED, c["k"], prec_name)
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], r=1, prec=prec, seed=SEED)
+    outs = []
+    for mb in ("1", "4096"):
+        monkeypatch.setenv("SMP_PI_WINDOW_MB", mb)
+        outs.append(_sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"]))
+    for At, Bt, na2, nb2 in outs:
+        assert _col_rel(At, oAt) < tol and _col_rel(Bt, oBt) < tol
+        assert np.allclose(na2, ona2, rtol=1e-6, atol=0) and np.allclose(nb2, onb2, rtol=1e-6, atol=0)
+    assert _col_rel(outs[0][0], outs[1][0].T.astype(np.float64)) < 1e-6
+    assert _col_rel(outs[0][1], outs[1][1].T.astype(np.float64)) < 1e-6
+
+
+def test_sketch_bf16_streaming_pushes_span_windows(api, ctx, monkeypatch):
+    """Streaming pushes larger than one Pi window (1 MiB: 1,280 rows at
+    k = 400) and out of order."""
+    monkeypatch.setenv("SMP_PI_WINDOW_MB", "1")
+    d, n1, n2, k = 9000, 130, 70, 400
+    A, B, Ad, Bd = latent(d, n1, n2)
+    cx = ctx
+    p = _bf16_params(api, d, n1, n2, k, seed=SEED)
+    st = cx.smp_sketch_begin(p)
+    for l0, l1 in [(5000, 9000), (0, 17), (17, 5000)]:
+        cx.smp_sketch_push(st, Ad[l0:l1], Bd[l0:l1], l0)
+    At = torch.empty(n1, k, device=DEV)
+    Bt = torch.empty(n2, k, device=DEV)
+    na2 = torch.empty(n1, device=DEV)
+    nb2 = torch.empty(n2, device=DEV)
+    cx.smp_sketch_end(st, At, Bt, na2, nb2)
+    torch.cuda.synchronize()
+    cx.smp_sketch_free(st)
+    oAt, oBt, ona2, _ = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, k, "bf16")
+    assert _col_rel(At.cpu().numpy(), oAt) < TOL_SKETCH
+    assert _col_rel(Bt.cpu().numpy(), oBt) < TOL_SKETCH
+    assert np.allclose(na2.cpu().numpy(), ona2, rtol=1e-6)
+
+
 def _pi_rows_bf16(seed, k, rows_c, d):
     """R(Z(c, l)) / sqrt(k) for selected sketch rows c and all l < d."""
     out = np.empty((len(rows_c), d))

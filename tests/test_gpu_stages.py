@@ -314,16 +314,24 @@ def _waltmin_parity(api, ctx, name):
 
 @pytest.mark.parametrize("T", [0, 3])
 def test_waltmin_trim_fires_like_the_oracle(api, ctx, T):
-    """Alg. 2 step 6 on a crafted case where it fires: one spike M~_00
-    dominates R, but ||A_0|| is tiny, so ||U0_0|| exceeds
-    8 sqrt(r) ||A_0|| / ||A||_F and row 0 of U0 is zeroed. The GPU's trimmed
-    initial factors (T = 0) and the iterates from them (T = 3) match the
-    oracle's product, and row 0 of the T = 0 output is zero."""
+    """Alg. 2 step 6 on a crafted case where it fires: a spike M~_00 = 100
+    on top of a rank-2 signal (30 a b^T + 10 c d^T, unit a, b, c, d) makes
+    the first singular vector almost e_0, but ||A_0|| is tiny, so ||U0_0||
+    exceeds 8 sqrt(r) ||A_0|| / ||A||_F and row 0 of U0 is zeroed. The
+    trimmed U0 keeps rank r (singular values 1 and 0.011), so every later
+    least-squares problem has one solution and the product does not depend
+    on how the fixed factor is orthonormalised. (A spike alone would leave
+    a zero column, and the solution would then depend on the basis chosen
+    for it.) The GPU's trimmed initial factors (T = 0) and the iterates from
+    them (T = 3) match the oracle's product, and row 0 of the T = 0 output is
+    zero."""
     n1 = n2 = 20
     r = 2
-    M = np.zeros((n1, n2))
-    M[0, 0] = 100.0
-    M[1:, 1:] = np.random.default_rng(0).standard_normal((19, 19)) * 0.01
+    rng = np.random.default_rng(0)
+    a, b, c, dd = (x / np.linalg.norm(x) for x in (rng.standard_normal(n1), rng.standard_normal(n2),
+                                                   rng.standard_normal(n1), rng.standard_normal(n2)))
+    M = 30.0 * np.outer(a, b) + 10.0 * np.outer(c, dd) + 0.01 * rng.standard_normal((n1, n2))
+    M[0, 0] += 100.0
     rows, cols = [a.ravel() for a in np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")]
     w = np.ones(rows.size)
     na32 = np.ones(n1, dtype=np.float32)
