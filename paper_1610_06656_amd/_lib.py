@@ -25,6 +25,7 @@ SMP_PREC_FP8 = 2
 SMP_OMEGA_REUSE = 0
 SMP_OMEGA_SPLIT = 1
 SMP_B_IS_A = 1
+SMP_SAMPLE_MULTINOMIAL = 2
 
 
 class SmpParams(ctypes.Structure):
