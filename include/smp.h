@@ -202,6 +202,18 @@ smp_status smp_sample(smp_ctx *ctx, const smp_params *p, const float *na2, const
 smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt,
                         const float *na2, const float *nb2, smp_omega *om);
 
+/* Allocation-free form of smp_estimate, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, layouts and results (bit for bit),
+ * but the FP64 column-norm scratch lives in a file-scope device array of
+ * 16 MiB that the library holds on every device it runs on until the process
+ * ends; no call allocates or frees anything. Limit: n1 + n2 <= 1,048,576,
+ * else SMP_ERR_CAPACITY (nothing launched). All calls on one GPU share that
+ * GPU's array: calls that overlap on one GPU (different streams, threads or
+ * contexts) race and must be serialised by the caller. */
+smp_status smp_estimate_noalloc(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt,
+                                const float *na2, const float *nb2, smp_omega *om);
+
 /* ---- a6-a8: WAltMin (Appendix A, Alg. 2) and the canonical output -----------
  * Init: top-r left/right singular subspace of R = w .* P_Omega0(M~) by block
  * subspace iteration; rows of U0 with ||U0_i|| > 8 sqrt(r) sqrt(na2_i / F_A)

@@ -83,6 +83,9 @@ EXPORTS = {
                                   ctypes.POINTER(SmpOmega)]),
     "smp_estimate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SmpOmega)]),
+    "smp_estimate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(SmpOmega)]),
     "smp_waltmin": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.POINTER(SmpOmega),
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "smp_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),

@@ -189,6 +189,12 @@ class Context:
                                           _ptr(Bt, torch.float32, "Bt"), _ptr(na2, torch.float32, "na2"),
                                           _ptr(nb2, torch.float32, "nb2"), ctypes.byref(o)))
 
+    def smp_estimate_noalloc(self, p, At, Bt, na2, nb2, om):
+        o = om.struct()
+        self._check(self.lib.smp_estimate_noalloc(self.h, ctypes.byref(p), _ptr(At, torch.float32, "At"),
+                                                  _ptr(Bt, torch.float32, "Bt"), _ptr(na2, torch.float32, "na2"),
+                                                  _ptr(nb2, torch.float32, "nb2"), ctypes.byref(o)))
+
     def smp_waltmin(self, p, om, na2, U, V, sigma=None):
         o = om.struct()
         self._check(self.lib.smp_waltmin(self.h, ctypes.byref(p), ctypes.byref(o), _ptr(na2, torch.float32, "na2"),

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -154,6 +155,40 @@ struct smp_sketch_state {
   bool ended;
 };
 
+// ---- allocation-free estimate: its scratch in a file-scope device array -----
+// na, nb (sketch-column norms) and sa, sb (data-column norms), FP64, for at
+// most kNoAllocMaxCols = n1 + n2 columns: 2 * 2^20 doubles = 16 MiB on every
+// device the library runs on, held until the process ends. Every call on a
+// device shares that device's copy; the kernels write every entry they read,
+// so nothing is cleared between calls.
+namespace {
+constexpr int64_t kNoAllocMaxCols = int64_t(1) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxCols];
+
+// The device address of `scratch` on the current device (which is `device`),
+// looked up once per device. The array's name is only a host-side stand-in.
+static hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+static void *scratch_for(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 struct smp_ctx_bufs {
   Buf sketch, samplews, head, omega, est, wm, mn;
 };
@@ -199,6 +234,13 @@ smp_status smp_create(smp_ctx **ctx, int device, void *hip_stream) {
   if (hipHostMalloc((void **)&c->host_pinned, 8 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(nullptr, SMP_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
+  }
+  const hipError_t se = scratch_setup(device);   // with `device` current (set above)
+  if (se != hipSuccess) {
+    hipGetLastError();
+    hipHostFree(c->host_pinned);
+    delete c;
+    return fail(nullptr, SMP_ERR_DEVICE, std::string("scratch symbol lookup failed: ") + hipGetErrorString(se));
   }
   c->ws = new smp_ctx_bufs();
   *ctx = c;
@@ -518,6 +560,30 @@ smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, cons
   double *nb = take<double>(c, n2);
   double *sa = take<double>(c, n1);
   double *sb = take<double>(c, n2);
+  if (same) {
+    nb = na;
+    sb = sa;
+  }
+  SMP_HIP(ctx, smp::estimate_run(At, Bt, na2, nb2, n1, n2, p->k, na, nb, sa, sb, *om, ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_estimate_noalloc(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt,
+                                const float *na2, const float *nb2, smp_omega *om) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  if (!At || !Bt || !na2 || !nb2 || !om) return fail(ctx, SMP_ERR_INVALID_ARG, "input pointer is NULL");
+  if (om->n1 != p->n1 || om->n2 != p->n2) return fail(ctx, SMP_ERR_INVALID_ARG, "om grid differs from params");
+  if (om->nnz > 0 && (!om->mt_csr || !om->mt_csc)) return fail(ctx, SMP_ERR_INVALID_ARG, "mt arrays are NULL");
+  const int64_t n1 = p->n1, n2 = p->n2;
+  if (n1 + n2 > kNoAllocMaxCols)
+    return fail(ctx, SMP_ERR_CAPACITY, "n1 + n2 = " + std::to_string(n1 + n2) +
+                                           " exceeds the allocation-free limit of " + std::to_string(kNoAllocMaxCols));
+  double *base = static_cast<double *>(scratch_for(ctx->device));
+  if (!base) return fail(ctx, SMP_ERR_DEVICE, "no scratch address for this device");
+  const bool same = At == Bt && na2 == nb2;
+  double *na = base, *nb = base + n1, *sa = base + n1 + n2, *sb = base + 2 * n1 + n2;
   if (same) {
     nb = na;
     sb = sa;

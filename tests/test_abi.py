@@ -110,6 +110,11 @@ def test_workspace_does_not_grow_with_d_through_pi(lib, prec):
     assert sizes[2] < 2_000_000_000
 
 
+def test_noalloc_estimate_without_context(lib):
+    p = _params()
+    assert lib.smp_estimate_noalloc(None, ctypes.byref(p), None, None, None, None, None) == _lib.SMP_ERR_INVALID_ARG
+
+
 def test_status_strings(lib):
     for s in range(8):
         assert lib.smp_status_str(s) and lib.smp_status_str(s) != b"unknown status"
