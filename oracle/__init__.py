@@ -18,9 +18,10 @@ Module map (each function cites the passage of the paper it follows):
 * ``waltmin``   Appendix A, Alg. 2: WAltMin init, trim, alternating solves
 * ``evaluate``  Section 4 "spectral norm error" and the best rank-r error
 * ``solve``     Alg. 1 end to end
+* ``baselines`` the comparison methods of Section 4: SVD(A~^T B~) and LELA
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test except
 those marked "parity unpinned" in their docstring.
 """
 
-from . import philox, gaussian, sketch, sample, multinomial, estimate, waltmin, evaluate, solve  # noqa: F401
+from . import philox, gaussian, sketch, sample, multinomial, estimate, waltmin, evaluate, solve, baselines  # noqa: F401
