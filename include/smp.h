@@ -147,7 +147,7 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes);
  * The sketch pass never holds all of Pi: the FP32 pass regenerates each
  * block of Pi inside the workgroup that multiplies it; the BF16 and FP8
  * passes draw Pi (already rounded, in the matrix-core operand order) one
- * window of data rows at a time into library scratch of at most 64 MiB
+ * window of data rows at a time into library scratch of at most 128 MiB
  * (smp_workspace_size does not grow with d through Pi) and multiply that
  * window before drawing the next. */
 smp_status smp_pi_fill(smp_ctx *ctx, const smp_params *p, int64_t l0, int64_t nrows, float *out);
@@ -213,6 +213,38 @@ smp_status smp_estimate(smp_ctx *ctx, const smp_params *p, const float *At, cons
  * contexts) race and must be serialised by the caller. */
 smp_status smp_estimate_noalloc(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt,
                                 const float *na2, const float *nb2, smp_omega *om);
+
+/* ---- comparison methods (Section 1 footnote; Section 4) ----------------------
+ * SVD(A~^T B~): the top-r SVD of the product of the sketches At (n1 x k),
+ * Bt (n2 x k) written by smp_sketch, without the rescaling of Eq. (2). Block
+ * subspace iteration on X = At Bt^T (p = min(r + 10, 64, n1, n2, k) columns,
+ * p->init_iters rounds, 0 = 8; Philox-seeded start) and a Rayleigh-Ritz step,
+ * all FP64 (the FP32 sketches widened exactly); output in the canonical form
+ * of smp_waltmin (orthonormal U, V, sigma descending; sigma NULL folds it into
+ * U). Needs r <= k. smp_solve_svd_sketch runs the sketch pass first (the same
+ * Pi as smp_solve) and synchronises at its end. */
+smp_status smp_svd_sketch(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt, double *U, double *V,
+                          double *sigma);
+smp_status smp_solve_svd_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                                int64_t ldb, double *U, double *V, double *sigma);
+
+/* LELA, the two-pass method (Section 4, "Comparison of SMP-PCA and LELA"):
+ * smp_column_norms is its first pass (na2[i] = ||A_i||^2, nb2 likewise; FP64
+ * partial sums over row blocks added in a fixed order, stored as FP32; with
+ * SMP_B_IS_A, B is ignored and nb2 receives a copy or may be NULL);
+ * smp_exact_entries its second (om->mt_csr and mt_csc receive the exact
+ * (A^T B)_ij on Omega: the plain GEMM A^T B by rocBLAS SGEMM over chunks of
+ * 65,536 rows, each chunk's FP32 product added into an FP64 accumulator, then
+ * gathered; n1 n2 x 12 bytes of library workspace). smp_lela runs the whole
+ * method: norms, the sample of Eq. (1) (p->flags selects the sampler as for
+ * smp_sample), exact entries, WAltMin and the canonical form, as smp_solve
+ * does after its sketch pass; it synchronises at its end. */
+smp_status smp_column_norms(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                            int64_t ldb, float *na2, float *nb2);
+smp_status smp_exact_entries(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                             int64_t ldb, smp_omega *om);
+smp_status smp_lela(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
+                    double *U, double *V, double *sigma);
 
 /* ---- a6-a8: WAltMin (Appendix A, Alg. 2) and the canonical output -----------
  * Init: top-r left/right singular subspace of R = w .* P_Omega0(M~) by block

@@ -83,6 +83,18 @@ EXPORTS = {
                                   ctypes.POINTER(SmpOmega)]),
     "smp_estimate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SmpOmega)]),
+    "smp_svd_sketch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "smp_solve_svd_sketch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "smp_column_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "smp_exact_entries": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.POINTER(SmpOmega)]),
+    "smp_lela": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "smp_estimate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(SmpOmega)]),

@@ -220,6 +220,35 @@ class Context:
                                        _ptr(Bp, torch.float32, "B", dense=False), Bp.stride(0), _ptr(U, torch.float64, "U"),
                                        _ptr(V, torch.float64, "V"), _ptr(sigma, torch.float64, "sigma")))
 
+    # ---- comparison methods (Section 4)
+    def smp_svd_sketch(self, p, At, Bt, U, V, sigma=None):
+        self._check(self.lib.smp_svd_sketch(self.h, ctypes.byref(p), _ptr(At, torch.float32, "At"),
+                                            _ptr(Bt, torch.float32, "Bt"), _ptr(U, torch.float64, "U"),
+                                            _ptr(V, torch.float64, "V"), _ptr(sigma, torch.float64, "sigma")))
+
+    def _ab(self, A, B):
+        if A.stride(1) != 1 or (B is not None and B.stride(1) != 1):
+            raise ValueError("A and B must have unit column stride")
+        Bp = B if B is not None else A
+        return (_ptr(A, torch.float32, "A", dense=False), A.stride(0), _ptr(Bp, torch.float32, "B", dense=False),
+                Bp.stride(0))
+
+    def smp_solve_svd_sketch(self, p, A, B, U, V, sigma=None):
+        self._check(self.lib.smp_solve_svd_sketch(self.h, ctypes.byref(p), *self._ab(A, B), _ptr(U, torch.float64, "U"),
+                                                  _ptr(V, torch.float64, "V"), _ptr(sigma, torch.float64, "sigma")))
+
+    def smp_column_norms(self, p, A, B, na2, nb2):
+        self._check(self.lib.smp_column_norms(self.h, ctypes.byref(p), *self._ab(A, B),
+                                              _ptr(na2, torch.float32, "na2"), _ptr(nb2, torch.float32, "nb2")))
+
+    def smp_exact_entries(self, p, A, B, om):
+        o = om.struct()
+        self._check(self.lib.smp_exact_entries(self.h, ctypes.byref(p), *self._ab(A, B), ctypes.byref(o)))
+
+    def smp_lela(self, p, A, B, U, V, sigma=None):
+        self._check(self.lib.smp_lela(self.h, ctypes.byref(p), *self._ab(A, B), _ptr(U, torch.float64, "U"),
+                                      _ptr(V, torch.float64, "V"), _ptr(sigma, torch.float64, "sigma")))
+
 
 def _job_dict(r):
     return {"status": int(r.status), "worker": int(r.worker), "queue_ms": float(r.queue_ms),

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libsmp.so")
 ARCH = os.environ.get("SMP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "server.cpp", "sketch.hip", "sketch_bf16.hip", "sketch_fp8.hip", "sample.hip", "sample_multi.hip",
-           "estimate.hip", "waltmin.hip"]
+           "estimate.hip", "waltmin.hip", "baselines.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -59,7 +59,10 @@ def build(verbose=False):
             if warn:
                 print(f"[{src}]\n" + "\n".join(warn), file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(_hipcc()))), "lib")
+    # rocBLAS serves the LELA baseline's plain GEMM (the exact entries of A^T B)
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{rocm_lib}", "-lrocblas", f"-Wl,-rpath,{rocm_lib}"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"linking libsmp.so failed:\n{res.stderr}")

@@ -190,7 +190,7 @@ static void *scratch_for(int device) {
 }
 
 struct smp_ctx_bufs {
-  Buf sketch, samplews, head, omega, est, wm, mn;
+  Buf sketch, samplews, head, omega, est, wm, mn, base;
 };
 
 namespace {
@@ -253,13 +253,14 @@ void smp_destroy(smp_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
   if (b) {
-    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn})
+    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base})
       if (x->p) hipFree(x->p);
     delete b;
   }
   if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
   for (hipEvent_t &e : ctx->events)
     if (e) hipEventDestroy(e);
+  smp::blas_destroy(ctx->blas);
   delete ctx;
 }
 
@@ -694,6 +695,160 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
   return SMP_OK;
 }
 
+// ---- comparison methods (Section 4) -------------------------------------------------
+
+smp_status smp_svd_sketch(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt, double *U, double *V,
+                          double *sigma) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  if (!At || !Bt || !U || !V) return fail(ctx, SMP_ERR_INVALID_ARG, "input or output pointer is NULL");
+  if (p->r > p->k) return fail(ctx, SMP_ERR_INVALID_ARG, "r must not exceed k (A~^T B~ has rank <= k)");
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.base, smp::svd_sketch_ws_bytes(p->n1, p->n2, p->k, p->r));
+  if (s != SMP_OK) return s;
+  const int iters = p->init_iters > 0 ? p->init_iters : 8;
+  SMP_HIP(ctx, smp::svd_sketch_run(At, Bt, p->n1, p->n2, p->k, p->r, iters, p->seed, U, V, sigma, b.base.p,
+                                   ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_solve_svd_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                                int64_t ldb, double *U, double *V, double *sigma) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string msg = check(p);
+  if (!msg.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, msg);
+  smp_params q = *p;
+  if (B == A && p->n1 == p->n2 && ldb == lda) q.flags |= SMP_B_IS_A;
+  const bool same = (q.flags & SMP_B_IS_A) != 0;
+  if (!A || lda < q.n1 || (!same && (!B || ldb < q.n2)))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "A/B is NULL or leading dimension too small");
+  if (!U || !V) return fail(ctx, SMP_ERR_INVALID_ARG, "U or V is NULL");
+  const int64_t n1 = q.n1, n2 = q.n2, k = q.k;
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.head, al(n1 * k * 4) + al(n2 * k * 4) + al(n1 * 4) + al(n2 * 4));
+  if (s != SMP_OK) return s;
+  char *hc = static_cast<char *>(b.head.p);
+  float *At = take<float>(hc, n1 * k);
+  float *Bt = take<float>(hc, n2 * k);
+  float *na2 = take<float>(hc, n1);
+  float *nb2 = take<float>(hc, n2);
+  s = smp_sketch(ctx, &q, A, lda, B, ldb, At, Bt, na2, nb2);
+  if (s != SMP_OK) return s;
+  s = smp_svd_sketch(ctx, &q, At, same ? At : Bt, U, V, sigma);
+  if (s != SMP_OK) return s;
+  SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_column_norms(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                            int64_t ldb, float *na2, float *nb2) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  const bool same = (p->flags & SMP_B_IS_A) != 0;
+  if (!A || lda < p->n1 || !na2) return fail(ctx, SMP_ERR_INVALID_ARG, "A or na2 is NULL or lda < n1");
+  if (!same && (!B || ldb < p->n2 || !nb2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B or nb2 is NULL or ldb < n2");
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.est, smp::norms_ws_bytes(p->n1, same ? p->n1 : p->n2));
+  if (s != SMP_OK) return s;
+  double *part = static_cast<double *>(b.est.p);
+  SMP_HIP(ctx, smp::column_norms(A, lda, p->d, p->n1, na2, part, ctx->stream));
+  if (same) {
+    if (nb2 && nb2 != na2)
+      SMP_HIP(ctx, hipMemcpyAsync(nb2, na2, (size_t)p->n1 * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    SMP_HIP(ctx, smp::column_norms(B, ldb, p->d, p->n2, nb2, part, ctx->stream));
+  }
+  return SMP_OK;
+}
+
+smp_status smp_exact_entries(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                             int64_t ldb, smp_omega *om) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  const bool same = (p->flags & SMP_B_IS_A) != 0;
+  if (same) {
+    B = A;
+    ldb = lda;
+  }
+  if (!A || !B || lda < p->n1 || ldb < p->n2 || !om) return fail(ctx, SMP_ERR_INVALID_ARG, "A, B or om is NULL");
+  if (lda > INT32_MAX || ldb > INT32_MAX) return fail(ctx, SMP_ERR_INVALID_ARG, "leading dimension too large");
+  if (om->n1 != p->n1 || om->n2 != p->n2) return fail(ctx, SMP_ERR_INVALID_ARG, "om grid differs from params");
+  if (om->nnz > 0 && (!om->mt_csr || !om->mt_csc)) return fail(ctx, SMP_ERR_INVALID_ARG, "mt arrays are NULL");
+  if (!ctx->blas && smp::blas_create(&ctx->blas) != hipSuccess) {
+    ctx->blas = nullptr;
+    return fail(ctx, SMP_ERR_DEVICE, "rocBLAS handle creation failed");
+  }
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.base, smp::exact_entries_ws_bytes(p->n1, p->n2));
+  if (s != SMP_OK) return s;
+  SMP_HIP(ctx, smp::exact_entries(ctx->blas, A, lda, B, ldb, p->d, p->n1, p->n2, *om, b.base.p, ctx->stream));
+  return SMP_OK;
+}
+
+smp_status smp_lela(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
+                    double *U, double *V, double *sigma) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string msg = check(p);
+  if (!msg.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, msg);
+  smp_params q = *p;
+  if (B == A && p->n1 == p->n2 && ldb == lda) q.flags |= SMP_B_IS_A;
+  const bool same = (q.flags & SMP_B_IS_A) != 0;
+  if (!A || lda < q.n1 || (!same && (!B || ldb < q.n2)))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "A/B is NULL or leading dimension too small");
+  if (!U || !V) return fail(ctx, SMP_ERR_INVALID_ARG, "U or V is NULL");
+  const int64_t n1 = q.n1, n2 = q.n2;
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.head, al(n1 * 4) + al(n2 * 4) + al((n1 + 2) * 8) + al((n2 + 2) * 8));
+  if (s != SMP_OK) return s;
+  char *hc = static_cast<char *>(b.head.p);
+  float *na2 = take<float>(hc, n1);
+  float *nb2 = take<float>(hc, n2);
+  int64_t *rp = take<int64_t>(hc, n1 + 2);
+  int64_t *cp = take<int64_t>(hc, n2 + 2);
+  // pass 1: column norms, then the sample of Eq. (1)
+  s = smp_column_norms(ctx, &q, A, lda, B, ldb, na2, same ? na2 : nb2);
+  if (s != SMP_OK) return s;
+  smp_omega om{};
+  om.n1 = n1;
+  om.n2 = n2;
+  om.row_ptr = rp;
+  om.col_ptr = cp;
+  s = smp_sample(ctx, &q, na2, same ? na2 : nb2, &om);
+  if (s != SMP_OK && s != SMP_ERR_CAPACITY) return s;
+  const int64_t nnz = om.nnz;
+  const bool split = q.omega_mode == SMP_OMEGA_SPLIT;
+  s = ensure(ctx, b.omega, std::max<size_t>(2 * (al(nnz * 4) + al(nnz * 8) + al(nnz * 8) + (split ? al(nnz) : 0)), 256));
+  if (s != SMP_OK) return s;
+  char *c = static_cast<char *>(b.omega.p);
+  om.cap = nnz;
+  om.col_idx = take<int32_t>(c, nnz);
+  om.w_csr = take<double>(c, nnz);
+  om.mt_csr = take<double>(c, nnz);
+  om.row_idx = take<int32_t>(c, nnz);
+  om.w_csc = take<double>(c, nnz);
+  om.mt_csc = take<double>(c, nnz);
+  om.sub_csr = split ? take<uint8_t>(c, nnz) : nullptr;
+  om.sub_csc = split ? take<uint8_t>(c, nnz) : nullptr;
+  smp::SampleWs ws;
+  if (nnz > 0) {
+    s = sample_ws(ctx, n1, n2, ws);
+    if (s != SMP_OK) return s;
+    SMP_HIP(ctx, sample_fill_any(ctx, &q, ws, om));
+  }
+  // pass 2: the exact entries on the sample, then WAltMin on them
+  s = smp_exact_entries(ctx, &q, A, lda, same ? A : B, same ? lda : ldb, &om);
+  if (s != SMP_OK) return s;
+  s = sample_ws(ctx, n1, n2, ws);
+  if (s != SMP_OK) return s;
+  s = waltmin_call(ctx, &q, &om, na2, U, V, sigma, ws.stats);
+  if (s != SMP_OK) return s;
+  SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return SMP_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -705,14 +860,15 @@ namespace smp {
 size_t ctx_workspace_bytes(const smp_ctx *ctx) {
   const auto *b = static_cast<const smp_ctx_bufs *>(ctx->ws);
   size_t s = 0;
-  for (const Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn}) s += x->bytes;
+  for (const Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base})
+    s += x->bytes;
   return s;
 }
 
 void ctx_release_workspace(smp_ctx *ctx) {
   auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
   hipStreamSynchronize(ctx->stream);
-  for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn}) {
+  for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base}) {
     if (x->p) hipFree(x->p);
     x->p = nullptr;
     x->bytes = 0;

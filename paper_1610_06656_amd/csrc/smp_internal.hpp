@@ -22,6 +22,8 @@ struct smp_ctx {
   int timing = 0;
   hipEvent_t events[10] = {};
   bool recorded[5] = {};
+  // rocBLAS handle of the LELA baseline's exact entries (created on first use)
+  void *blas = nullptr;
 };
 
 namespace smp {
@@ -62,7 +64,7 @@ SketchPlan sketch_plan_fp8(int k);
 // Stored-Pi passes draw Pi one window at a time into a buffer of at most
 // kPiWindowBytes (the window: pi_window_rows(pl) data rows, a whole number of
 // blocks), so the buffer does not grow with d.
-constexpr int64_t kPiWindowBytes = 64ll << 20;
+constexpr int64_t kPiWindowBytes = 128ll << 20;
 int64_t pi_window_rows(const SketchPlan &pl);
 
 // Bytes of the stored-Pi buffer a push of `rows` rows needs (0 unless
@@ -144,5 +146,21 @@ size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t nnz);
 hipError_t waltmin_run(const smp_params &p, const smp_omega &om, const float *na2, double *U, double *V,
                        double *sigma, void *ws, hipStream_t st,
                        const double *fa_in);   // F_A on the device, or null to sum it from na2
+
+// ---- comparison methods (Section 4) ----------------------------------------------
+// SVD(A~^T B~): top-r SVD of At Bt^T (At n1 x k, Bt n2 x k) by block subspace
+// iteration (`iters` rounds) and Rayleigh-Ritz, canonical output.
+size_t svd_sketch_ws_bytes(int64_t n1, int64_t n2, int k, int r);
+hipError_t svd_sketch_run(const float *At, const float *Bt, int64_t n1, int64_t n2, int k, int r, int iters,
+                          uint64_t seed, double *Uout, double *Vout, double *sigma, void *ws, hipStream_t st);
+// LELA: column norms (FP64 partials, `part` holds norms_ws_bytes), exact
+// entries A_i^T B_j on Omega (rocBLAS SGEMM chunks into an FP64 accumulator).
+size_t norms_ws_bytes(int64_t n1, int64_t n2);
+hipError_t column_norms(const float *X, int64_t ld, int64_t d, int64_t n, float *out, double *part, hipStream_t st);
+size_t exact_entries_ws_bytes(int64_t n1, int64_t n2);
+hipError_t exact_entries(void *blas, const float *A, int64_t lda, const float *B, int64_t ldb, int64_t d, int64_t n1,
+                         int64_t n2, const smp_omega &om, void *ws, hipStream_t st);
+hipError_t blas_create(void **blas);
+void blas_destroy(void *blas);
 
 }  // namespace smp

@@ -863,6 +863,71 @@ struct Ws {
   double *U, *V;    // n1*r, n2*r iterates
 };
 
+// ---- the dense low-rank operator X = S1 S2^T of the SVD(A~^T B~) baseline -----
+// S (n x k, FP32, row-major) times a block: the sketches enter as they are
+// (widened exactly to FP64), the products are FP64.
+
+// part[b][c][j] = sum over the rows i of block b of S[i][c] Y[i][j]. Thread
+// (c mod 64, j group g) keeps the columns j = g, g + 4, ... of one c.
+template <int JPT>
+__global__ __launch_bounds__(256) void tmul_partial_kernel(const float *__restrict__ S, int64_t n, int k,
+                                                           const double *__restrict__ Y, int p, int64_t rpb,
+                                                           double *__restrict__ part) {
+  const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int64_t i0 = (int64_t)blockIdx.y * rpb, i1 = i0 + rpb < n ? i0 + rpb : n;
+  double acc[JPT];
+#pragma unroll
+  for (int u = 0; u < JPT; ++u) acc[u] = 0.0;
+  const int cc = c < k ? c : k - 1;
+  for (int64_t i = i0; i < i1; ++i) {
+    const double sv = c < k ? (double)S[i * k + cc] : 0.0;
+    const double *y = Y + i * p;
+#pragma unroll
+    for (int u = 0; u < JPT; ++u) {
+      const int j = g + 4 * u;
+      acc[u] = fma(sv, y[j < p ? j : p - 1], acc[u]);
+    }
+  }
+  if (c < k) {
+#pragma unroll
+    for (int u = 0; u < JPT; ++u) {
+      const int j = g + 4 * u;
+      if (j < p) part[((int64_t)blockIdx.y * k + c) * p + j] = acc[u];
+    }
+  }
+}
+
+// T[c][j] = sum of the partials in block order.
+__global__ void tmul_reduce_kernel(const double *__restrict__ part, int nblk, int64_t kp, double *__restrict__ T) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < kp; x += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * kp + x];
+    T[x] = s;
+  }
+}
+
+// X[i][j] = sum_c S[i][c] T[c][j]: one wave per row, lane j; four
+// accumulators over c mod 4, added in a fixed order.
+__global__ __launch_bounds__(256) void smul_kernel(const float *__restrict__ S, int64_t n, int k,
+                                                   const double *__restrict__ T, int p, double *__restrict__ X) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const float *row = S + i * k;
+  const int j = lane < p ? lane : p - 1;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int c = 0;
+  for (; c + 4 <= k; c += 4) {
+    a0 = fma((double)row[c], T[(int64_t)c * p + j], a0);
+    a1 = fma((double)row[c + 1], T[(int64_t)(c + 1) * p + j], a1);
+    a2 = fma((double)row[c + 2], T[(int64_t)(c + 2) * p + j], a2);
+    a3 = fma((double)row[c + 3], T[(int64_t)(c + 3) * p + j], a3);
+  }
+  for (; c < k; ++c) a0 = fma((double)row[c], T[(int64_t)c * p + j], a0);
+  if (lane < p) X[i * p + lane] = (a0 + a1) + (a2 + a3);
+}
+
 constexpr int kGramBlocks = 64;
 
 template <typename T>
@@ -1006,6 +1071,65 @@ void canonical(const Ws &w, const double *U, int64_t n1, const double *V, int64_
 }
 
 }  // namespace
+
+// ---- SVD(A~^T B~): the top-r SVD of the product of the sketches ---------------
+constexpr int kSvdOversample = 10;
+constexpr int kTmulBlocks = 32;
+
+static int svd_p(int64_t n1, int64_t n2, int k, int r) {
+  const int64_t lim = std::min<int64_t>(std::min(n1, n2), k);
+  return std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(lim, r + kSvdOversample)));
+}
+
+size_t svd_sketch_ws_bytes(int64_t n1, int64_t n2, int k, int r) {
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const int p = svd_p(n1, n2, k, r);
+  return carve_bytes(n1, n2, p, r) + al((size_t)k * p * 8) + al((size_t)kTmulBlocks * k * p * 8);
+}
+
+// out (n_out x p) = S_out (S_in^T Y) with S_in n_in x k, S_out n_out x k.
+static void lowrank_apply(const float *S_in, int64_t n_in, const float *S_out, int64_t n_out, int k, const double *Y,
+                          int p, double *T, double *tpart, double *out, hipStream_t st) {
+  const int nblk = (int)std::min<int64_t>(kTmulBlocks, std::max<int64_t>(1, (n_in + 255) / 256));
+  const int64_t rpb = (n_in + nblk - 1) / nblk;
+  const dim3 grid((unsigned)((k + 63) / 64), (unsigned)nblk);
+  if (p <= 16)
+    hipLaunchKernelGGL(tmul_partial_kernel<4>, grid, dim3(256), 0, st, S_in, n_in, k, Y, p, rpb, tpart);
+  else if (p <= 32)
+    hipLaunchKernelGGL(tmul_partial_kernel<8>, grid, dim3(256), 0, st, S_in, n_in, k, Y, p, rpb, tpart);
+  else
+    hipLaunchKernelGGL(tmul_partial_kernel<16>, grid, dim3(256), 0, st, S_in, n_in, k, Y, p, rpb, tpart);
+  hipLaunchKernelGGL(tmul_reduce_kernel, dim3(cdiv((int64_t)k * p, 256)), dim3(256), 0, st, tpart, nblk,
+                     (int64_t)k * p, T);
+  hipLaunchKernelGGL(smul_kernel, dim3(cdiv(n_out, 4)), dim3(256), 0, st, S_out, n_out, k, T, p, out);
+}
+
+hipError_t svd_sketch_run(const float *At, const float *Bt, int64_t n1, int64_t n2, int k, int r, int iters,
+                          uint64_t seed, double *Uout, double *Vout, double *sigma, void *wsbase, hipStream_t st) {
+  const int p = svd_p(n1, n2, k, r);
+  Ws w = carve_ws(wsbase, n1, n2, p, r);
+  char *c = static_cast<char *>(wsbase) + carve_bytes(n1, n2, p, r);
+  double *T = reinterpret_cast<double *>(c);
+  double *tpart = reinterpret_cast<double *>(c + ((size_t)k * p * 8 + 255) / 256 * 256);
+  // block subspace iteration on X = At Bt^T (n1 x n2) from a Philox-seeded start
+  hipLaunchKernelGGL(gaussian_block_kernel, dim3(cdiv(n2 * ((p + 3) / 4), 256)), dim3(256), 0, st, n2, p, seed, w.Y);
+  orth(w, w.Y, n2, p, st);
+  for (int it = 0; it < iters; ++it) {
+    lowrank_apply(Bt, n2, At, n1, k, w.Y, p, T, tpart, w.X, st);   // X = At (Bt^T Y)
+    orth(w, w.X, n1, p, st);
+    lowrank_apply(At, n1, Bt, n2, k, w.X, p, T, tpart, w.Y, st);   // Y = Bt (At^T X)
+    orth(w, w.Y, n2, p, st);
+  }
+  lowrank_apply(Bt, n2, At, n1, k, w.Y, p, T, tpart, w.X, st);
+  // Rayleigh-Ritz: X^T X = W diag(lam) W^T; U = X W_r lam^-1/2, V = Y W_r, sigma = lam^1/2
+  jacobi_eig(w.part, gram(w, w.X, n1, p, st), p, r, w.Mu, w.Mv, w.sig, st);
+  apply2(w.X, n1, w.Mu, w.U, nullptr, nullptr, w.Y, n2, w.Mv, w.V, p, r, st);
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
+  double *sig_out = sigma ? sigma : w.sig;
+  canonical(w, w.U, n1, w.V, n2, r, Uout, Vout, sig_out, st);
+  if (!sigma) hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, Uout, n1, r, sig_out);
+  return hipGetLastError();
+}
 
 size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t /*nnz*/) {
   const int p = std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample));
