@@ -1,20 +1,26 @@
 """Benchmark of the SMP-PCA hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload c3|c2|batch|serve] [--legs bf16,fp8,fp32,ab]
+                    [--no-c2] [--no-mix]
 
 A step is one smp_solve (Alg. 1 end to end: sketch pass, sampling, rescaled-JL
-estimates, WAltMin, canonical form) over the dense FP32 workload
-d = 200,000, n1 = n2 = 2,000, k = 400, r = 10, T = 10, m = 4 n r ln n
-(latent rank 10, noise 0.1, column scaling (j+1)^-0.5), with A and B already
-resident in HBM. `value` is input bytes consumed per second, 4 d (n1+n2) / t,
-of the BF16-sketch solve (sketch GEMM operands rounded to bfloat16, FP32
-accumulation, FP64 WAltMin); the same solve with the FP32 sketch ("fp32") and
-with the FP8 E4M3 block-scaled sketch ("fp8") is timed beside it, and each
-leg's spectral error is reported.
+estimates, WAltMin, canonical form) with A and B already resident in HBM.
 
-Also reported: the dominant kernel's roofline (the sketch pass, timed with HIP
-events on the library's stream), per-stage times, solves/s with p50/p99
-latency, and the FP64 CPU oracle timed on the host.
+Default workload (one JSON line): the large precision workload,
+d = 1,000,000, n1 = n2 = 4,096, k = 1,024, r = 20, T = 10, m = 4 n r ln n
+(latent rank 20, noise 0.05, column scaling (j+1)^-0.7). `value` is input
+bytes consumed per second, 4 d (n1+n2) / t, of the whole BF16-sketch solve
+(sketch GEMM operands rounded to bfloat16, FP32 accumulation, FP64 WAltMin).
+Beside it, at the same size: the FP8 E4M3 block-scaled sketch ("fp8"), the
+plain FP32 sketch ("fp32") and the PCA case A = B ("ab", BF16), each with its
+spectral error; the roofline of the BF16 sketch pass (MFMA-bound at this size)
+with its HBM rate; the d = 200,000, n = 2,000, k = 400 workload ("c2", BF16
+and FP32); the batching mix (512 jobs) and the Poisson serving mix ("batch",
+"serve", solves/s and p50/p99 latency, BF16 vs FP32); and the FP64 CPU
+oracle's sketch pass timed on the host over a stated number of rows.
+
+--workload c2|batch|serve prints the single-workload lines instead.
 """
 
 import argparse
@@ -32,7 +38,9 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0   # dense
 PEAK_FP8_MFMA_TFLOPS = 5000.0    # dense
 PEAK_HBM_GBPS = 8000.0
-CFG = dict(d=200_000, n1=2000, n2=2000, R=10, sigma=0.1, alpha=0.5, k=400, r=10, T=10)
+C2 = dict(d=200_000, n1=2000, n2=2000, R=10, sigma=0.1, alpha=0.5, k=400, r=10, T=10)
+C3 = dict(d=1_000_000, n1=4096, n2=4096, R=20, sigma=0.05, alpha=0.7, k=1024, r=20, T=10)
+LEGS = ("bf16", "fp8", "fp32", "ab")
 
 
 def parse():
@@ -42,10 +50,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
-                    help="rows of the CPU-oracle sample (0: all d rows)")
-    ap.add_argument("--workload", choices=("c2", "batch", "serve"), default="c2",
-                    help="c2: the headline solve (default); batch: 512 jobs of the batching mix through the "
-                         "server; serve: Poisson arrivals of the serving mix")
+                    help="rows of the CPU-oracle sketch sample (0: 60,000 at the large workload, all at c2)")
+    ap.add_argument("--workload", choices=("c3", "c2", "batch", "serve"), default="c3",
+                    help="c3: the large precision workload with every leg (default); c2: d = 200,000 only; "
+                         "batch: 512 jobs of the batching mix; serve: Poisson arrivals of the serving mix")
+    ap.add_argument("--legs", default=",".join(LEGS), help="legs of the large workload to run (bf16,fp8,fp32,ab)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the d = 200,000 leg of the default line")
+    ap.add_argument("--no-mix", action="store_true", help="skip the batching and serving legs of the default line")
+    ap.add_argument("--no-errors", action="store_true", help="skip the spectral errors (profiling runs)")
     ap.add_argument("--workers", type=int, default=4, help="server worker threads (batch, serve)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window of the serve workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -77,12 +89,14 @@ def pct(xs, q):
     return xs[i]
 
 
-def cpu_baseline(A, B, c, m, seed, rows):
+def _threads():
+    from threadpoolctl import threadpool_info
+    return int(max([t.get("num_threads", 1) for t in threadpool_info()] or [1]))
+
+
+def cpu_baseline_pipeline(A, B, c, m, seed, rows):
     """The oracle as it stands (FP64 numpy) on a bounded sample of the same
     workload: the first `rows` rows of A and B, the full downstream pipeline."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
-
     from oracle import solve as osolve
 
     d_s = min(rows or c["d"], c["d"])
@@ -91,18 +105,47 @@ def cpu_baseline(A, B, c, m, seed, rows):
     t0 = time.perf_counter()
     osolve.smp_pca(a, b, c["r"], c["k"], m, c["T"], seed)
     dt = time.perf_counter() - t0
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     gbytes = 4.0 * d_s * (c["n1"] + c["n2"]) / 1e9
-    return {"value": gbytes / dt, "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+    return {"value": gbytes / dt, "unit": "GB/s", "cores": _threads(), "kind": "oracle",
             "sample": f"full SMP-PCA pipeline on the first {d_s} of {c['d']} rows "
                       f"({gbytes:.2f} GB of FP32 input), {dt:.1f} s"}
 
 
-def spectral_error(A, B, U, s, V, iters=60):
-    """||A^T B - U diag(s) V^T||_2 / ||A^T B||_2 by power iteration in FP64
-    on the device (evaluation only, outside the timed region)."""
+def cpu_baseline_sketch(A, B, c, seed, rows):
+    """The oracle's single pass (Alg. 1 step 2: Pi drawn from the counter,
+    FP64 products, exact column norms) over the first `rows` rows of A and B.
+    At this size the oracle's downstream stages alone (a dense 4,096^2 SVD and
+    the per-row solves) take over a minute of host time, so the bounded sample
+    is the pass, which is also what the metric's GB/s measures."""
+    from oracle import sketch as osk
+
+    d_s = min(rows, c["d"])
+    a = A[:d_s].cpu().numpy()
+    b = B[:d_s].cpu().numpy()
+    t0 = time.perf_counter()
+    osk.sketch(a, b, seed, c["k"])
+    dt = time.perf_counter() - t0
+    gbytes = 4.0 * d_s * (c["n1"] + c["n2"]) / 1e9
+    return {"value": gbytes / dt, "unit": "GB/s", "cores": _threads(), "kind": "oracle",
+            "sample": f"oracle sketch pass (Pi generation, FP64 products, column norms) over the first {d_s} of "
+                      f"{c['d']} rows ({gbytes:.2f} GB of FP32 input), {dt:.1f} s; the oracle's downstream stages "
+                      f"are not in the sample"}
+
+
+def product_fp64(A, B, chunk=1 << 16):
+    """A^T B in FP64 on the device, accumulated over row chunks (B None: A^T A)."""
     import torch
-    M = A.double().T @ B.double()
+    M = torch.zeros(A.shape[1], (A if B is None else B).shape[1], dtype=torch.float64, device=A.device)
+    for l0 in range(0, A.shape[0], chunk):
+        a = A[l0:l0 + chunk].double()
+        M += a.T @ (a if B is None else B[l0:l0 + chunk].double())
+    return M
+
+
+def spectral_error(M, U, s, V, iters=60):
+    """||M - U diag(s) V^T||_2 / ||M||_2 by power iteration in FP64 on the
+    device (evaluation only, outside the timed region)."""
+    import torch
     E = M - (U * s[None, :]) @ V.T
 
     def norm2(X):
@@ -116,52 +159,85 @@ def spectral_error(A, B, U, s, V, iters=60):
     return norm2(E) / norm2(M)
 
 
-def run_leg(ctx, api, A, B, c, seed, prec, steps, warmup):
+def run_leg(ctx, api, A, B, c, seed, prec, steps, warmup, same=False):
     import torch
     dev = A.device
-    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed, prec=prec)
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed, prec=prec, b_is_a=same)
     U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=dev)
     V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=dev)
     s = torch.empty(c["r"], dtype=torch.float64, device=dev)
+    Bx = A if same else B
     # inside the timed region only the sketch pass is bracketed by HIP events
     # (the roofline's kernel time); each event pair leaves the GPU idle for
     # about 10 us at a stage boundary, so the other stages are timed after it
     ctx.smp_set_timing(2)
     for _ in range(warmup):
-        ctx.smp_solve(p, A, B, U, V, s)
+        ctx.smp_solve(p, A, Bx, U, V, s)
     torch.cuda.synchronize()
     lat, sketch = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
-        ctx.smp_solve(p, A, B, U, V, s)          # synchronises at its end
+        ctx.smp_solve(p, A, Bx, U, V, s)          # synchronises at its end
         lat.append((time.perf_counter() - ts) * 1e3)
         sketch.append(ctx.smp_stage_times()["sketch"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall / steps * 1e3
-    in_bytes = 4.0 * c["d"] * (c["n1"] + c["n2"])
+    in_bytes = 4.0 * c["d"] * (c["n1"] + (0 if same else c["n2"]))
+    flops = (2.0 * c["k"] + 4.0) * c["d"] * (c["n1"] + (0 if same else c["n2"]))
     # stage breakdown: further solves with every stage bracketed (not timed)
     ctx.smp_set_timing(1)
     stages = []
     for _ in range(max(1, min(steps, 5))):
-        ctx.smp_solve(p, A, B, U, V, s)
+        ctx.smp_solve(p, A, Bx, U, V, s)
         stages.append(ctx.smp_stage_times())
     ctx.smp_set_timing(0)
     avg = {k: sum(st[k] for st in stages) / len(stages) for k in stages[0]}
     avg["sketch"] = sum(sketch) / len(sketch)
-    return dict(p=p, ms_step=ms_step, in_bytes=in_bytes, avg=avg, lat=lat,
-                err=spectral_error(A, B, U, s, V))
+    return dict(p=p, ms_step=ms_step, in_bytes=in_bytes, flops=flops, avg=avg, lat=lat, out=(U, s, V))
 
 
-def leg_summary(leg):
+def leg_summary(leg, err=None):
     sk = leg["avg"]["sketch"]
-    return {"ms_per_step": round(leg["ms_step"], 4), "solves_per_s": round(1e3 / leg["ms_step"], 3),
-            "latency_ms": {"p50": round(pct(leg["lat"], 50), 4), "p99": round(pct(leg["lat"], 99), 4)},
-            "stages_ms": {k: round(v, 4) for k, v in leg["avg"].items()},
-            "sketch_pass_gbps": round(leg["in_bytes"] / (sk / 1e3) / 1e9, 2),
-            "sketch_pass_hbm_frac": round(leg["in_bytes"] / (sk / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
-            "spectral_error": leg["err"]}
+    out = {"ms_per_step": round(leg["ms_step"], 4), "solves_per_s": round(1e3 / leg["ms_step"], 3),
+           "input_gbps": round(leg["in_bytes"] / (leg["ms_step"] / 1e3) / 1e9, 2),
+           "latency_ms": {"p50": round(pct(leg["lat"], 50), 4), "p99": round(pct(leg["lat"], 99), 4)},
+           "stages_ms": {k: round(v, 4) for k, v in leg["avg"].items()},
+           "sketch_pass_gbps": round(leg["in_bytes"] / (sk / 1e3) / 1e9, 2),
+           "sketch_pass_hbm_frac": round(leg["in_bytes"] / (sk / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
+           "sketch_pass_tflops": round(leg["flops"] / (sk / 1e3) / 1e12, 2)}
+    if err is not None:
+        out["spectral_error"] = err
+    return out
+
+
+def roofline(leg, prec, traffic_name, kernel):
+    """The sketch pass against the roofline that bounds it at this size:
+    the matrix cores when flops / peak exceeds bytes / HBM peak, else HBM."""
+    sk = leg["avg"]["sketch"] / 1e3
+    peak_mfma = {"bf16": PEAK_BF16_MFMA_TFLOPS, "fp8": PEAK_FP8_MFMA_TFLOPS, "fp32": PEAK_FP32_MFMA_TFLOPS}[prec]
+    tflops = leg["flops"] / sk / 1e12
+    gbps = leg["in_bytes"] / sk / 1e9
+    mfma_bound = leg["flops"] / (peak_mfma * 1e12) > leg["in_bytes"] / (PEAK_HBM_GBPS * 1e9)
+    base = {"traffic": recorded_traffic(traffic_name), "kernel": kernel, "kernel_ms": round(sk * 1e3, 4),
+            "bytes_per_launch": leg["in_bytes"], "flops_per_launch": leg["flops"],
+            "hbm_gbps": round(gbps, 2), "hbm_frac": round(gbps / PEAK_HBM_GBPS, 4),
+            "mfma_tflops": round(tflops, 2), "mfma_frac": round(tflops / peak_mfma, 4)}
+    if mfma_bound:
+        return dict({"bound": "mfma", "achieved": round(tflops, 2), "peak": peak_mfma, "unit": "TFLOP/s",
+                     "frac": round(tflops / peak_mfma, 4)}, **base)
+    return dict({"bound": "hbm", "achieved": round(gbps, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                 "frac": round(gbps / PEAK_HBM_GBPS, 4)}, **base)
+
+
+KERNELS = {
+    "bf16": "BF16 sketch pass: per Pi window pi_store_bf16_kernel then sketch_bf16_stored_kernel "
+            "(v_mfma_f32_16x16x32_bf16), then the tail launch, timed together",
+    "fp8": "FP8 sketch pass: per Pi window pi_store_fp8_kernel then sketch_fp8_stored_kernel "
+           "(v_mfma_scale_f32_16x16x128_f8f6f4), then the tail launch, timed together",
+    "fp32": "sketch_kernel (v_mfma_f32_16x16x4f32, Pi regenerated per tile)",
+}
 
 
 def _pools(spec, count, d, n, seed, dev):
@@ -225,6 +301,46 @@ def run_mix(api, jobs, pools, large_pool, prec, workers, arrivals=None):
     return out
 
 
+def mix_legs(api, args, pools, large_pool, dev):
+    """The batching mix (512 jobs at once) and the serving mix (Poisson
+    arrivals, 5% large jobs), each with BF16 and FP32 sketches."""
+    import torch
+
+    import smp_inputs
+    b, sv = smp_inputs.BATCH, smp_inputs.SERVE
+    seed = smp_inputs.SEED_BASE
+    out = {}
+    batch_jobs = smp_inputs.job_mix(b["jobs"], seed)
+    g = torch.Generator().manual_seed(seed)
+    arrivals, t = [], 0.0
+    while True:
+        t += float(torch.empty(1).exponential_(sv["rate_per_s"], generator=g))
+        if t > args.serve_seconds:
+            break
+        arrivals.append(t)
+    serve_jobs = smp_inputs.job_mix(len(arrivals), seed, large_frac=sv["large_frac"])
+    for name, jobs, arr in (("batch", batch_jobs, None), ("serve", serve_jobs, arrivals)):
+        if name == "serve" and large_pool is None:
+            continue
+        legs = {}
+        for leg, prec in (("bf16", api.SMP_PREC_BF16), ("fp32", api.SMP_PREC_FP32)):
+            run_mix(api, jobs[:8], pools, large_pool, prec, args.workers)          # warm-up (workspaces, code)
+            legs[leg] = run_mix(api, jobs, pools, large_pool, prec, args.workers, arr)
+        legs["bf16_vs_fp32_solves"] = round(legs["bf16"]["solves_per_s"] / legs["fp32"]["solves_per_s"], 3)
+        out[name] = legs
+    out["batch"]["workload"] = (f"{b['jobs']} independent jobs submitted at once: d uniform in [10k, 200k], n1 = n2 "
+                                f"uniform in [128, 2048], r in {{5, 10, 20}}, k = r * uniform{{4..20}}, T = 10, "
+                                f"m = 4nr ln n; latent rank 10, noise 0.1, column scale (j+1)^-0.5; each job's own "
+                                f"seed for Pi and the coins; inputs are top-left blocks of {b['pools']} resident "
+                                f"200000 x 2048 pairs; {args.workers} server workers")
+    if "serve" in out:
+        out["serve"]["workload"] = (f"Poisson arrivals at {sv['rate_per_s']:.0f} jobs/s for {args.serve_seconds:.1f} s "
+                                    f"({len(arrivals)} jobs): the batching mix plus {100 * sv['large_frac']:.0f}% large "
+                                    f"jobs (d = 1M, n1 = n2 = 4096, r = 20, k = r * uniform{{4..20}}; the large "
+                                    f"workload's matrices); {args.workers} server workers")
+    return out
+
+
 def main_mix(args):
     import torch
 
@@ -235,35 +351,81 @@ def main_mix(args):
     b, sv = smp_inputs.BATCH, smp_inputs.SERVE
     seed = smp_inputs.SEED_BASE
     pools = _pools(b, b["pools"], b["d"][1], b["n"][1], seed, dev)
-    if args.workload == "batch":
-        jobs = smp_inputs.job_mix(b["jobs"], seed)
-        large_pool, arrivals = None, None
-        desc = (f"{b['jobs']} independent jobs: d uniform in [10k, 200k], n1 = n2 uniform in [128, 2048], "
-                f"r in {{5, 10, 20}}, k = r * uniform{{4..20}}, T = 10, m = 4nr ln n; latent rank 10, noise 0.1, "
-                f"column scale (j+1)^-0.5; inputs are top-left blocks of {b['pools']} resident 200000 x 2048 pairs")
-    else:
+    large_pool = None
+    if args.workload == "serve":
         L = sv["large"]
-        large_pool = _pools(sv, 1, L["d"], L["n"], seed + 1, dev)[0]
-        g = torch.Generator().manual_seed(seed)
-        arrivals, t = [], 0.0
-        while True:
-            t += float(torch.empty(1).exponential_(sv["rate_per_s"], generator=g))
-            if t > args.serve_seconds:
-                break
-            arrivals.append(t)
-        jobs = smp_inputs.job_mix(len(arrivals), seed, large_frac=sv["large_frac"])
-        desc = (f"Poisson arrivals at {sv['rate_per_s']:.0f} jobs/s for {args.serve_seconds:.1f} s: the batching mix "
-                f"plus {100 * sv['large_frac']:.0f}% large jobs (d = 1M, n1 = n2 = 4096, r = 20; latent rank 20, "
-                f"noise 0.05, column scale (j+1)^-0.7); inputs are blocks of resident pairs")
+        large_pool = _pools(sv, 1, L["d"], L["n"], seed, dev)[0]
     torch.cuda.synchronize()
-    legs = {}
-    for name, prec in (("bf16", api.SMP_PREC_BF16), ("fp32", api.SMP_PREC_FP32)):
-        run_mix(api, jobs[:8], pools, large_pool, prec, args.workers)          # warm-up (workspaces, code)
-        legs[name] = run_mix(api, jobs, pools, large_pool, prec, args.workers, arrivals)
-    out = {"metric": METRIC, "workload": args.workload, "value": legs["bf16"]["solves_per_s"], "unit": "solves/s",
+    mix = mix_legs(api, args, pools, large_pool, dev)
+    leg = mix[args.workload]
+    out = {"metric": METRIC, "workload": args.workload, "value": leg["bf16"]["solves_per_s"], "unit": "solves/s",
            "n_gpus": 1, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
-           "config": {"workload": desc, "workers": args.workers}, "bf16": legs["bf16"], "fp32": legs["fp32"]}
+           "config": {"workload": leg["workload"], "workers": args.workers}, "bf16": leg["bf16"], "fp32": leg["fp32"],
+           "bf16_vs_fp32_solves": leg["bf16_vs_fp32_solves"]}
     print(json.dumps(out), flush=True)
+
+
+def c2_legs(api, ctx, args, dev, seed, precs=("bf16", "fp32", "fp8")):
+    """The d = 200,000, n = 2,000, k = 400 workload: its legs and errors."""
+    import torch
+
+    import smp_inputs
+    c = C2
+    A, B = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], seed, device=dev)
+    torch.cuda.synchronize()
+    M = None if args.no_errors else product_fp64(A, B)
+    prec_of = {"bf16": api.SMP_PREC_BF16, "fp32": api.SMP_PREC_FP32, "fp8": api.SMP_PREC_FP8}
+    legs = {}
+    for name in precs:
+        leg = run_leg(ctx, api, A, B, c, seed, prec_of[name], args.steps, args.warmup)
+        err = None if M is None else spectral_error(M, *leg["out"])
+        legs[name] = dict(leg_summary(leg, err),
+                          roofline=roofline(leg, name, f"sketch_{name}_c2_traffic", KERNELS[name]))
+    return A, B, legs
+
+
+def main_c2(args):
+    import torch
+
+    import smp_inputs
+    from paper_1610_06656_amd import api
+
+    dev = torch.device("cuda:0")
+    seed = smp_inputs.SEED_BASE
+    ctx = api.Context(0)
+    precs = [x for x in args.legs.split(",") if x in ("bf16", "fp32", "fp8")]
+    assert "bf16" in precs, "--legs must include bf16"
+    A, B, legs = c2_legs(api, ctx, args, dev, seed, precs=precs)
+    c = C2
+    bf = legs["bf16"]
+    out = {"metric": METRIC, "value": bf["input_gbps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": bf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "SMP-PCA end to end, d=200000, n1=n2=2000, k=400, r=10, T=10, m=4nr ln n",
+                      "d": c["d"], "n1": c["n1"], "n2": c["n2"], "k": c["k"], "r": c["r"], "T": c["T"]},
+           "roofline": bf["roofline"]}
+    out.update(legs)
+    if "fp32" in legs:
+        out["bf16_vs_fp32_solves"] = round(legs["fp32"]["ms_per_step"] / bf["ms_per_step"], 3)
+    if args.copy_calibration:
+        copy_calibration(dev, out)
+    if not args.no_cpu_baseline:
+        p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed)
+        out["cpu_baseline"] = cpu_baseline_pipeline(A, B, c, p.m, seed, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+def copy_calibration(dev, out):
+    """One plain device copy of 2^30 bytes: the reference dispatch that scales
+    rocprofv3's FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = 1 << 30
 
 
 def main():
@@ -272,90 +434,94 @@ def main():
         print(json.dumps({"error": "one GPU only: --gpus must be 1 (sharding across GPUs "
                                    "is not built)"}))
         sys.exit(2)
-    if args.workload != "c2":
+    if args.workload in ("batch", "serve"):
         return main_mix(args)
+    if args.workload == "c2":
+        return main_c2(args)
     import torch
 
     import smp_inputs
     from paper_1610_06656_amd import api
 
     dev = torch.device("cuda:0")
-    c = CFG
     seed = smp_inputs.SEED_BASE
+    legs_wanted = [x for x in args.legs.split(",") if x]
+    assert legs_wanted and all(x in LEGS for x in legs_wanted), f"--legs: a subset of {LEGS}"
+    head = "bf16" if "bf16" in legs_wanted else legs_wanted[0]   # profiling runs may time one other leg only
+    c = C3
     A, B = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], seed, device=dev)
     torch.cuda.synchronize()
     ctx = api.Context(0)
-
-    fp32 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_FP32, args.steps, args.warmup)
-    bf16 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_BF16, args.steps, args.warmup)
-    fp8 = run_leg(ctx, api, A, B, c, seed, api.SMP_PREC_FP8, args.steps, args.warmup)
-
-    in_bytes = bf16["in_bytes"]
-    ms_step = bf16["ms_step"]
-    value = in_bytes / (ms_step / 1e3) / 1e9
-    sk_bf16 = bf16["avg"]["sketch"]
-    sk_fp32 = fp32["avg"]["sketch"]
-    sk_fp8 = fp8["avg"]["sketch"]
-    flops = (2.0 * c["k"] + 4.0) * c["d"] * (c["n1"] + c["n2"])
-    fp32_tflops = flops / (sk_fp32 / 1e3) / 1e12
-    hbm_gbps = in_bytes / (sk_bf16 / 1e3) / 1e9
-    p = bf16["p"]
+    prec_of = {"bf16": api.SMP_PREC_BF16, "fp8": api.SMP_PREC_FP8, "fp32": api.SMP_PREC_FP32, "ab": api.SMP_PREC_BF16}
+    runs = {}
+    for name in legs_wanted:
+        runs[name] = run_leg(ctx, api, A, B, c, seed, prec_of[name], args.steps, args.warmup, same=(name == "ab"))
+    # spectral errors (outside every timed region)
+    errs = {}
+    if not args.no_errors:
+        M = product_fp64(A, B)
+        for name in legs_wanted:
+            if name != "ab":
+                errs[name] = spectral_error(M, *runs[name]["out"])
+        del M
+        if "ab" in runs:
+            Maa = product_fp64(A, None)
+            errs["ab"] = spectral_error(Maa, *runs["ab"]["out"])
+            del Maa
+        torch.cuda.empty_cache()
+    legs = {}
+    for name in legs_wanted:
+        prec = "bf16" if name == "ab" else name
+        legs[name] = dict(leg_summary(runs[name], errs.get(name)),
+                          roofline=roofline(runs[name], prec, f"sketch_{name}_c3_traffic", KERNELS[prec]))
+    bf = runs[head]
+    value = bf["in_bytes"] / (bf["ms_step"] / 1e3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(value, 3),
         "unit": "GB/s",
+        "value_is": "input bytes 4 d (n1+n2) per second of the whole BF16 smp_solve (inputs resident in HBM); "
+                    "the sketch pass alone: roofline.hbm_gbps and roofline.mfma_tflops",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(bf["ms_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "SMP-PCA end to end, dense latent-rank-10 A and B (noise 0.1, column scale "
-                               "(j+1)^-0.5), d=200000, n1=n2=2000, k=400, r=10, T=10, m=4nr ln n; BF16 sketch "
-                               "GEMM (FP32 accumulate, FP32 compensated norms), FP64 sampling weights, "
-                               "estimates and WAltMin", "d": c["d"], "n1": c["n1"], "n2": c["n2"], "k": c["k"],
-                   "r": c["r"], "T": c["T"], "m": round(p.m, 3), "input_gb": round(in_bytes / 1e9, 3)},
-        "roofline": {"bound": "hbm", "achieved": round(hbm_gbps, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(hbm_gbps / PEAK_HBM_GBPS, 4),
-                     "traffic": recorded_traffic("sketch_bf16_c2_traffic"),
-                     "kernel": "BF16 sketch pass: pi_store_bf16_kernel, then sketch_bf16_stored_kernel "
-                               "(v_mfma_f32_16x16x32_bf16) main and tail launch, timed together",
-                     "mfma_tflops": round(flops / (sk_bf16 / 1e3) / 1e12, 2),
-                     "mfma_frac": round(flops / (sk_bf16 / 1e3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4),
-                     "kernel_ms": round(sk_bf16, 4), "bytes_per_launch": in_bytes},
-        "solves_per_s": round(1e3 / ms_step, 3),
-        "latency_ms": {"p50": round(pct(bf16["lat"], 50), 4), "p99": round(pct(bf16["lat"], 99), 4)},
-        "spectral_error": bf16["err"],
-        "bf16": leg_summary(bf16),
-        "fp32": dict(leg_summary(fp32), roofline={
-            "bound": "mfma", "achieved": round(fp32_tflops, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(fp32_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
-            "traffic": recorded_traffic("sketch_fp32_c2_traffic"),
-            "kernel": "sketch_kernel (v_mfma_f32_16x16x4f32)", "kernel_ms": round(sk_fp32, 4),
-            "flops_per_launch": flops}),
-        "fp8": dict(leg_summary(fp8), roofline={
-            "bound": "hbm", "achieved": round(in_bytes / (sk_fp8 / 1e3) / 1e9, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(in_bytes / (sk_fp8 / 1e3) / 1e9 / PEAK_HBM_GBPS, 4), "traffic": recorded_traffic("sketch_fp8_c2_traffic"),
-            "kernel": "FP8 sketch pass: pi_store_fp8_kernel, then sketch_fp8_stored_kernel "
-                      "(v_mfma_scale_f32_16x16x128_f8f6f4) main and tail launch, timed together",
-            "kernel_ms": round(sk_fp8, 4), "bytes_per_launch": in_bytes,
-            "mfma_tflops": round(flops / (sk_fp8 / 1e3) / 1e12, 2),
-            "mfma_frac": round(flops / (sk_fp8 / 1e3) / 1e12 / PEAK_FP8_MFMA_TFLOPS, 4)}),
-        "bf16_vs_fp32_solves": round(fp32["ms_step"] / bf16["ms_step"], 3),
+        "config": {"workload": "SMP-PCA end to end, dense latent-rank-20 A and B (noise 0.05, column scale "
+                               "(j+1)^-0.7), d=1000000, n1=n2=4096, k=1024, r=20, T=10, m=4nr ln n; BF16 sketch "
+                               "GEMM (FP32 accumulate, FP32 compensated norms), FP64 sampling weights, estimates "
+                               "and WAltMin", "d": c["d"], "n1": c["n1"], "n2": c["n2"], "k": c["k"],
+                   "r": c["r"], "T": c["T"], "m": round(bf["p"].m, 3), "input_gb": round(bf["in_bytes"] / 1e9, 3)},
+        "roofline": legs[head]["roofline"],
+        "solves_per_s": round(1e3 / bf["ms_step"], 3),
+        "latency_ms": legs[head]["latency_ms"],
+        "spectral_error": errs.get(head),
     }
+    out.update(legs)
+    if "fp32" in runs and head == "bf16":
+        out["bf16_vs_fp32_solves"] = round(runs["fp32"]["ms_step"] / bf["ms_step"], 3)
     if args.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = 1 << 30
+        copy_calibration(dev, out)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, B, c, p.m, seed, args.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline_sketch(A, B, c, seed, args.cpu_rows or 60_000)
+    if not args.no_c2:
+        A2, B2, c2 = c2_legs(api, ctx, args, dev, seed, precs=("bf16", "fp32"))
+        c2["bf16_vs_fp32_solves"] = round(c2["fp32"]["ms_per_step"] / c2["bf16"]["ms_per_step"], 3)
+        c2["workload"] = "d=200000, n1=n2=2000, k=400, r=10, T=10; latent rank 10, noise 0.1, column scale (j+1)^-0.5"
+        out["c2"] = c2
+        del A2, B2
+    if not args.no_mix:
+        import smp_inputs as si
+        b = si.BATCH
+        torch.cuda.empty_cache()
+        pools = _pools(b, b["pools"], b["d"][1], b["n"][1], seed, dev)
+        torch.cuda.synchronize()
+        out.update(mix_legs(api, args, pools, (A, B), dev))
+        del pools
     print(json.dumps(out), flush=True)
 
 
