@@ -16,9 +16,12 @@ Beside it, at the same size: the FP8 E4M3 block-scaled sketch ("fp8"), the
 plain FP32 sketch ("fp32") and the PCA case A = B ("ab", BF16), each with its
 spectral error; the roofline of the BF16 sketch pass (MFMA-bound at this size)
 with its HBM rate; the d = 200,000, n = 2,000, k = 400 workload ("c2", BF16
-and FP32); the batching mix (512 jobs) and the Poisson serving mix ("batch",
-"serve", solves/s and p50/p99 latency, BF16 vs FP32); and the FP64 CPU
-oracle's sketch pass timed on the host over a stated number of rows.
+and FP32, and the paper's comparison methods LELA and SVD(A~^T B~) beside
+SMP-PCA with their errors); the one-coin-per-entry and the row-wise
+multinomial samplers ("sampler", n up to 100,000); the batching mix (512 jobs)
+and the Poisson serving mix ("batch", "serve", solves/s and p50/p99 latency,
+BF16 vs FP32); and the FP64 CPU oracle's sketch pass timed on the host over a
+stated number of rows.
 
 --workload c2|batch|serve prints the single-workload lines instead.
 """
@@ -50,7 +53,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
-                    help="rows of the CPU-oracle sketch sample (0: 60,000 at the large workload, all at c2)")
+                    help="rows of the CPU-oracle sketch sample (0: 200,000 at the large workload, all at c2)")
     ap.add_argument("--workload", choices=("c3", "c2", "batch", "serve"), default="c3",
                     help="c3: the large precision workload with every leg (default); c2: d = 200,000 only; "
                          "batch: 512 jobs of the batching mix; serve: Poisson arrivals of the serving mix")
@@ -384,6 +387,64 @@ def c2_legs(api, ctx, args, dev, seed, precs=("bf16", "fp32", "fp8")):
     return A, B, legs
 
 
+def methods_c2(api, ctx, A, B, dev, seed, reps=5):
+    """The paper's comparison (Section 4) at d = 200,000, n = 2,000, k = 400,
+    r = 10 on the same matrices: the best rank-r error, LELA (two passes,
+    exact entries), SVD(A~^T B~) and SMP-PCA (BF16 sketch); ms per solve and
+    spectral error of each."""
+    import torch
+    c = C2
+    M = product_fp64(A, B)
+    sv = torch.linalg.svdvals(M)
+    out = {"optimal_error": (sv[c["r"]] / sv[0]).item()}
+    for name, fn, prec in (("smp_pca_bf16", ctx.smp_solve, api.SMP_PREC_BF16), ("lela", ctx.smp_lela, api.SMP_PREC_FP32),
+                           ("svd_sketch_bf16", ctx.smp_solve_svd_sketch, api.SMP_PREC_BF16)):
+        p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed, prec=prec)
+        U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=dev)
+        V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=dev)
+        s = torch.empty(c["r"], dtype=torch.float64, device=dev)
+        fn(p, A, B, U, V, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn(p, A, B, U, V, s)
+        torch.cuda.synchronize()
+        out[name] = {"ms": round((time.perf_counter() - t0) / reps * 1e3, 3),
+                     "error": float(torch.linalg.matrix_norm(M - (U * s[None, :]) @ V.T, 2) / sv[0])}
+    return out
+
+
+def sampler_legs(api, ctx, dev, reps=5):
+    """smp_sample with one coin per grid entry (Alg. 1 step 3) against the
+    row-wise multinomial draws of Appendix D, on squared norms with
+    power-law column profiles, n1 = n2 = n, m = 4 n r ln n."""
+    import numpy as np
+    import torch
+    from paper_1610_06656_amd.api import Omega
+    out = []
+    for n, r in ((2000, 10), (30000, 5), (100000, 5)):
+        rng = np.random.default_rng(0)
+        na2 = torch.from_numpy((rng.standard_normal(n) ** 2 * np.arange(1, n + 1) ** -0.8).astype(np.float32)).to(dev)
+        nb2 = torch.from_numpy((rng.standard_normal(n) ** 2 * np.arange(1, n + 1) ** -0.5).astype(np.float32)).to(dev)
+        row = {"n1": n, "n2": n, "r": r}
+        for sampler in ("binomial", "multinomial"):
+            if sampler == "binomial" and n > 30000:
+                continue                      # 10^10 coins
+            p = api.make_params(100, n, n, 8, r, sampler=sampler)
+            om = Omega(n, n, int(p.m + n + 64 + 6 * p.m ** 0.5), dev)
+            ctx.smp_sample(p, na2, nb2, om)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                nnz = ctx.smp_sample(p, na2, nb2, om)
+            row[sampler + "_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+            row[sampler + "_omega"] = int(nnz)
+            row["m"] = round(p.m, 1)
+            del om
+        out.append(row)
+    return out
+
+
 def main_c2(args):
     import torch
 
@@ -507,13 +568,16 @@ def main():
     if args.copy_calibration:
         copy_calibration(dev, out)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_sketch(A, B, c, seed, args.cpu_rows or 60_000)
+        out["cpu_baseline"] = cpu_baseline_sketch(A, B, c, seed, args.cpu_rows or 200_000)
     if not args.no_c2:
         A2, B2, c2 = c2_legs(api, ctx, args, dev, seed, precs=("bf16", "fp32"))
         c2["bf16_vs_fp32_solves"] = round(c2["fp32"]["ms_per_step"] / c2["bf16"]["ms_per_step"], 3)
         c2["workload"] = "d=200000, n1=n2=2000, k=400, r=10, T=10; latent rank 10, noise 0.1, column scale (j+1)^-0.5"
+        if not args.no_errors:
+            c2["methods"] = methods_c2(api, ctx, A2, B2, dev, seed)
         out["c2"] = c2
         del A2, B2
+        out["sampler"] = sampler_legs(api, ctx, dev)
     if not args.no_mix:
         import smp_inputs as si
         b = si.BATCH
