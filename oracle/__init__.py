@@ -12,6 +12,7 @@ Module map (each function cites the passage of the paper it follows):
 * ``philox``    counter-based generator (Philox4x32-10, Salmon et al., SC'11)
 * ``gaussian``  Box-Muller transform of two 24-bit uniforms
 * ``sketch``    Alg. 1 step 2 / Section 2 "Step 1": Pi, sketches, column norms
+* ``srht``      the subsampled randomized Hadamard transform as Pi (Section 4, Spark)
 * ``sample``    Eq. (1) and Alg. 1 step 3: q, q-hat, Omega, weights
 * ``multinomial`` Appendix D "Sampling": row-wise multinomial draws of Omega
 * ``estimate``  Eq. (2): rescaled-JL estimates on Omega
@@ -24,4 +25,4 @@ Parity status: every function is pinned by a ``-m "not gpu"`` test except
 those marked "parity unpinned" in their docstring.
 """
 
-from . import philox, gaussian, sketch, sample, multinomial, estimate, waltmin, evaluate, solve, baselines  # noqa: F401
+from . import philox, gaussian, sketch, sample, multinomial, estimate, waltmin, evaluate, solve, baselines, srht  # noqa: F401

@@ -10,6 +10,7 @@ import numpy as np
 from . import sketch as _sketch
 from . import sample as _sample
 from . import multinomial as _multinomial
+from . import srht as _srht
 from . import estimate as _estimate
 from . import waltmin as _waltmin
 
@@ -21,12 +22,15 @@ def default_m(n1, n2, r):
     return 4.0 * n * r * math.log(n)
 
 
-def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None, sampler="binomial"):
+def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None, sampler="binomial", sketch_kind="gaussian"):
     """Run Alg. 1. A: d x n1, B: d x n2 or None (A = B, Section 3 Remark 3).
     sketch_fmt: None for the FP64 pass, or a narrow format ("bf16", "fp8") whose
     rounded operands form the sketches (``oracle.sketch.sketch_lowp``).
     sampler: "binomial" (Alg. 1 step 3, ``oracle.sample``) or "multinomial"
     (the row-wise sampler of Appendix D, ``oracle.multinomial``).
+    sketch_kind: "gaussian" (Alg. 1 step 2) or "srht" (the subsampled
+    randomized Hadamard transform of the Spark implementation, ``oracle.srht``;
+    FP64 only).
     Returns a dict with the output factors and every intermediate:
       At, Bt, na2, nb2      sketches and squared column norms (step 2)
       omega                  oracle.sample.Omega (step 3)
@@ -34,7 +38,10 @@ def smp_pca(A, B, r, k, m, T, seed, split=False, sketch_fmt=None, sampler="binom
       U, V                   WAltMin output (step 5), U V^T the approximation
       Uc, sigma, Vc          canonical SVD form of U V^T
     """
-    if sketch_fmt is None:
+    if sketch_kind == "srht":
+        assert sketch_fmt is None, "the SRHT sketch is defined in FP64 only"
+        At, Bt, na2, nb2 = _srht.sketch(A, B, seed, k)
+    elif sketch_fmt is None:
         At, Bt, na2, nb2 = _sketch.sketch(A, B, seed, k)
     else:
         At, Bt, na2, nb2 = _sketch.sketch_lowp(A, B, seed, k, sketch_fmt)
