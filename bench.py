@@ -13,8 +13,8 @@ d = 1,000,000, n1 = n2 = 4,096, k = 1,024, r = 20, T = 10, m = 4 n r ln n
 bytes consumed per second, 4 d (n1+n2) / t, of the whole BF16-sketch solve
 (sketch GEMM operands rounded to bfloat16, FP32 accumulation, FP64 WAltMin).
 Beside it, at the same size: the FP8 E4M3 block-scaled sketch ("fp8"), the
-plain FP32 sketch ("fp32") and the PCA case A = B ("ab", BF16), each with its
-spectral error; the roofline of the BF16 sketch pass (MFMA-bound at this size)
+plain FP32 sketch ("fp32"), the PCA case A = B ("ab", BF16) and the SRHT
+sketch ("srht", FP32), each with its spectral error; the roofline of the BF16 sketch pass (MFMA-bound at this size)
 with its HBM rate; the d = 200,000, n = 2,000, k = 400 workload ("c2", BF16
 and FP32, and the paper's comparison methods LELA and SVD(A~^T B~) beside
 SMP-PCA with their errors); the one-coin-per-entry and the row-wise
@@ -43,7 +43,7 @@ PEAK_FP8_MFMA_TFLOPS = 5000.0    # dense
 PEAK_HBM_GBPS = 8000.0
 C2 = dict(d=200_000, n1=2000, n2=2000, R=10, sigma=0.1, alpha=0.5, k=400, r=10, T=10)
 C3 = dict(d=1_000_000, n1=4096, n2=4096, R=20, sigma=0.05, alpha=0.7, k=1024, r=20, T=10)
-LEGS = ("bf16", "fp8", "fp32", "ab")
+LEGS = ("bf16", "fp8", "fp32", "ab", "srht")
 
 
 def parse():
@@ -162,10 +162,11 @@ def spectral_error(M, U, s, V, iters=60):
     return norm2(E) / norm2(M)
 
 
-def run_leg(ctx, api, A, B, c, seed, prec, steps, warmup, same=False):
+def run_leg(ctx, api, A, B, c, seed, prec, steps, warmup, same=False, sketch="gaussian"):
     import torch
     dev = A.device
-    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed, prec=prec, b_is_a=same)
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed, prec=prec, b_is_a=same,
+                        sketch=sketch)
     U = torch.empty(c["n1"], c["r"], dtype=torch.float64, device=dev)
     V = torch.empty(c["n2"], c["r"], dtype=torch.float64, device=dev)
     s = torch.empty(c["r"], dtype=torch.float64, device=dev)
@@ -513,10 +514,12 @@ def main():
     A, B = smp_inputs.latent_pair(c["d"], c["n1"], c["n2"], c["R"], c["sigma"], c["alpha"], seed, device=dev)
     torch.cuda.synchronize()
     ctx = api.Context(0)
-    prec_of = {"bf16": api.SMP_PREC_BF16, "fp8": api.SMP_PREC_FP8, "fp32": api.SMP_PREC_FP32, "ab": api.SMP_PREC_BF16}
+    prec_of = {"bf16": api.SMP_PREC_BF16, "fp8": api.SMP_PREC_FP8, "fp32": api.SMP_PREC_FP32, "ab": api.SMP_PREC_BF16,
+               "srht": api.SMP_PREC_FP32}
     runs = {}
     for name in legs_wanted:
-        runs[name] = run_leg(ctx, api, A, B, c, seed, prec_of[name], args.steps, args.warmup, same=(name == "ab"))
+        runs[name] = run_leg(ctx, api, A, B, c, seed, prec_of[name], args.steps, args.warmup, same=(name == "ab"),
+                             sketch="srht" if name == "srht" else "gaussian")
     # spectral errors (outside every timed region)
     errs = {}
     if not args.no_errors:
@@ -532,6 +535,10 @@ def main():
         torch.cuda.empty_cache()
     legs = {}
     for name in legs_wanted:
+        if name == "srht":       # additions on the vector ALUs, no matrix-core work
+            legs[name] = dict(leg_summary(runs[name], errs.get(name)),
+                              kernel="srht_kernel: length-512 fast Walsh-Hadamard transforms of row chunks (FP32)")
+            continue
         prec = "bf16" if name == "ab" else name
         legs[name] = dict(leg_summary(runs[name], errs.get(name)),
                           roofline=roofline(runs[name], prec, f"sketch_{name}_c3_traffic", KERNELS[prec]))

@@ -83,7 +83,8 @@ typedef enum smp_omega_mode {
 
 enum {
   SMP_B_IS_A = 1u,              /* flags: B is A (PCA of A^T A, Section 3 Remark 3) */
-  SMP_SAMPLE_MULTINOMIAL = 2u   /* flags: draw Omega row by row (Appendix D) instead of one coin per entry */
+  SMP_SAMPLE_MULTINOMIAL = 2u,  /* flags: draw Omega row by row (Appendix D) instead of one coin per entry */
+  SMP_SKETCH_SRHT = 4u          /* flags: sketch with the subsampled randomized Hadamard transform (FP32 only) */
 };
 
 /* The problem statement of Section 2 (A, B, r, k, m, T) plus the seed. */
@@ -94,7 +95,7 @@ typedef struct smp_params {
   int32_t T;          /* WAltMin iterations; 0 <= T <= 1000 */
   int32_t prec;       /* smp_precision of the sketch GEMM */
   int32_t omega_mode; /* smp_omega_mode */
-  uint32_t flags;     /* SMP_B_IS_A | SMP_SAMPLE_MULTINOMIAL */
+  uint32_t flags;     /* SMP_B_IS_A | SMP_SAMPLE_MULTINOMIAL | SMP_SKETCH_SRHT */
   double m;           /* sample-count parameter of Eq. (1); > 0 */
   uint64_t seed;      /* Philox key */
   int32_t init_iters; /* subspace iterations of the WAltMin init; 0 = default (2) */
@@ -159,6 +160,17 @@ smp_status smp_pi_fill(smp_ctx *ctx, const smp_params *p, int64_t l0, int64_t nr
  * compensated FP32 sums per lane and an FP64 combine. */
 smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
                       int64_t ldb, float *At, float *Bt, float *na2, float *nb2);
+/* With SMP_SKETCH_SRHT in p->flags (and p->prec == SMP_PREC_FP32) the pass
+ * sketches with the subsampled randomized Hadamard transform instead of the
+ * Gaussian Pi (Section 4: the Spark implementation's choice):
+ * Pi[c,l] = sigma_l (-1)^popcount(rho_c & l) / sqrt(k), with sigma_l = +-1 from
+ * bit 0 of the Philox word of (row 0, column l) under tag 7 and rho_c < D (D the
+ * smallest power of two >= d) the low log2 D bits of the word of (row 0,
+ * column c) under tag 8 (rows of the Hadamard matrix drawn with replacement).
+ * Computed by length-512 fast Walsh-Hadamard transforms of row chunks in FP32
+ * (O(d n log 512 + d n k / 512) additions, no Gaussian draws); every other
+ * call (streaming pushes in any order, sampling, estimates, WAltMin, solve)
+ * works unchanged on its sketches. */
 
 /* Streaming form of the same pass: rows may be pushed in any order and any
  * block sizes (each row exactly once). The state holds O(k (n1+n2)) partial

@@ -26,6 +26,7 @@ SMP_OMEGA_REUSE = 0
 SMP_OMEGA_SPLIT = 1
 SMP_B_IS_A = 1
 SMP_SAMPLE_MULTINOMIAL = 2
+SMP_SKETCH_SRHT = 4
 
 
 class SmpParams(ctypes.Structure):

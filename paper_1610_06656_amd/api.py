@@ -50,16 +50,20 @@ def default_m(n1, n2, r):
 
 
 def make_params(d, n1, n2, k, r, T=10, m=None, seed=161006656, prec=_lib.SMP_PREC_FP32,
-                omega_mode=_lib.SMP_OMEGA_REUSE, b_is_a=False, init_iters=0, sampler="binomial"):
+                omega_mode=_lib.SMP_OMEGA_REUSE, b_is_a=False, init_iters=0, sampler="binomial", sketch="gaussian"):
     """smp_params; sampler "binomial" (one coin per entry) or "multinomial"
-    (row-wise draws, SMP_SAMPLE_MULTINOMIAL)."""
+    (row-wise draws, SMP_SAMPLE_MULTINOMIAL); sketch "gaussian" or "srht"
+    (SMP_SKETCH_SRHT, FP32)."""
     if sampler not in ("binomial", "multinomial"):
         raise ValueError(f"unknown sampler {sampler!r}")
+    if sketch not in ("gaussian", "srht"):
+        raise ValueError(f"unknown sketch {sketch!r}")
     p = SmpParams()
     p.d, p.n1, p.n2 = int(d), int(n1), int(n2)
     p.k, p.r, p.T = int(k), int(r), int(T)
     p.prec, p.omega_mode = int(prec), int(omega_mode)
-    p.flags = (_lib.SMP_B_IS_A if b_is_a else 0) | (_lib.SMP_SAMPLE_MULTINOMIAL if sampler == "multinomial" else 0)
+    p.flags = ((_lib.SMP_B_IS_A if b_is_a else 0) | (_lib.SMP_SAMPLE_MULTINOMIAL if sampler == "multinomial" else 0)
+               | (_lib.SMP_SKETCH_SRHT if sketch == "srht" else 0))
     p.m = float(default_m(n1, n2, r) if m is None else m)
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.init_iters = int(init_iters)

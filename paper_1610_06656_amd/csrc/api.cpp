@@ -56,7 +56,8 @@ std::string check(const smp_params *p) {
   if (p->omega_mode != SMP_OMEGA_REUSE && p->omega_mode != SMP_OMEGA_SPLIT) return "unknown omega_mode";
   if (p->init_iters < 0 || p->init_iters > 1000) return "init_iters must be in [0, 1000]";
   if (p->reserved != 0) return "reserved must be 0";
-  if (p->flags & ~(uint32_t)(SMP_B_IS_A | SMP_SAMPLE_MULTINOMIAL)) return "unknown flags";
+  if (p->flags & ~(uint32_t)(SMP_B_IS_A | SMP_SAMPLE_MULTINOMIAL | SMP_SKETCH_SRHT)) return "unknown flags";
+  if ((p->flags & SMP_SKETCH_SRHT) && p->prec != SMP_PREC_FP32) return "the SRHT sketch is FP32 only";
   if ((p->flags & SMP_B_IS_A) && p->n1 != p->n2) return "SMP_B_IS_A needs n1 == n2";
   if ((p->flags & SMP_SAMPLE_MULTINOMIAL) && p->m > 1e12) return "m too large for the multinomial sampler";
   if ((p->n1 + 1) * 4 > INT32_MAX || p->n2 > INT32_MAX / 4) return "n1, n2 too large for int32 entry indices";
@@ -80,7 +81,19 @@ constexpr int64_t kFp32RowsPerSplit = 32768;
 //   cost(S) = rounds * slots / total + 2 S kpad / w,
 // with at least 256 rows per split and, for the FP32 pass, at most
 // kFp32RowsPerSplit.
+// The sketch pass a parameter set selects: the SRHT (SMP_SKETCH_SRHT) or the
+// Gaussian pass in the given operand precision.
+SketchPlan plan_for(const smp_params *p) {
+  if (p->flags & SMP_SKETCH_SRHT) {
+    SketchPlan pl = smp::sketch_plan_srht(p->k);
+    pl.d = p->d;
+    return pl;
+  }
+  return smp::sketch_plan(p->k, p->prec);
+}
+
 int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
+  if (pl.srht) return smp::srht_splits(pl, d, n1, n2);
   const int64_t tiles = (n1 + pl.ncol_tile - 1) / pl.ncol_tile + (n2 + pl.ncol_tile - 1) / pl.ncol_tile;
   const int64_t per = (int64_t)pl.kt * tiles;
   const int64_t slots = smp::sketch_slots(pl);
@@ -296,7 +309,7 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes) {
   const std::string m = check(p);
   if (!m.empty()) return fail(nullptr, SMP_ERR_INVALID_ARG, m);
   if (!bytes) return fail(nullptr, SMP_ERR_INVALID_ARG, "bytes is NULL");
-  const SketchPlan pl = smp::sketch_plan(p->k, p->prec);
+  const SketchPlan pl = plan_for(p);
   const int S = choose_splits(pl, p->d, p->n1, p->n2);
   const int64_t nt = p->n1 + p->n2, k = p->k;
   size_t s = 0;
@@ -336,7 +349,7 @@ smp_status smp_sketch_begin(smp_ctx *ctx, const smp_params *p, smp_sketch_state 
   if (!s) return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "host allocation failed");
   s->ctx = ctx;
   s->p = *p;
-  s->plan = smp::sketch_plan(p->k, p->prec);
+  s->plan = plan_for(p);
   s->S = choose_splits(s->plan, p->d, p->n1, p->n2);
   const int64_t n2 = (p->flags & SMP_B_IS_A) ? 0 : p->n2;
   const int64_t nt = p->n1 + n2;
@@ -425,7 +438,7 @@ smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t
   if (!same && (!B || ldb < p->n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
   if (!At || !na2 || (!same && (!Bt || !nb2))) return fail(ctx, SMP_ERR_INVALID_ARG, "output pointer is NULL");
   // the one-shot pass keeps its partials in the context's workspace
-  const SketchPlan pl = smp::sketch_plan(p->k, p->prec);
+  const SketchPlan pl = plan_for(p);
   const int S = choose_splits(pl, p->d, p->n1, p->n2);
   const int64_t n2 = same ? 0 : p->n2;
   const int64_t nt = p->n1 + n2;

@@ -291,6 +291,7 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
                        int64_t n2, int64_t row0, int64_t rows, int k, uint64_t seed, int S, bool accumulate,
                        float *part, double *npart, void *pi_buf, hipStream_t st) {
   if (rows < 0) return hipErrorInvalidValue;
+  if (pl.srht) return srht_push(pl, A, lda, n1, B, ldb, n2, pl.d, row0, rows, k, seed, S, accumulate, part, npart, st);
   if (pl.pi_stored && rows > 0 && !pi_buf) return hipErrorInvalidValue;
   SkArgs g{};
   const int nct = pl.ncol_tile;

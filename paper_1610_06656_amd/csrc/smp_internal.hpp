@@ -50,7 +50,16 @@ struct SketchPlan {
   int pi_stored;        // 1: Pi is drawn window by window into a buffer that the pass streams
   int pi_rows;          // stored Pi: data rows per fragment block (32 BF16, 128 FP8)
   int pi_frag_bytes;    // stored Pi: bytes of one fragment (one MFMA A operand: 1024 BF16, 2048 FP8)
+  int srht = 0;         // 1: the SRHT pass (sketch_srht.hip); mt holds its accumulators per thread
+  int64_t d = 0;        // SRHT: rows of A and B (the Hadamard size is the next power of two)
 };
+
+// The SRHT pass (Section 4's Spark sketch): plan, splits and one push.
+SketchPlan sketch_plan_srht(int k);
+int srht_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2);
+hipError_t srht_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
+                     int64_t n2, int64_t d, int64_t row0, int64_t rows, int k, uint64_t seed, int S, bool accumulate,
+                     float *part, double *npart, hipStream_t st);
 
 // Partial-sketch slots a pass with S splits writes: S, plus one for the rows
 // the BF16 / FP8 main launch leaves to its tail launch.
