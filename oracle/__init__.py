@@ -13,6 +13,7 @@ Module map (each function cites the passage of the paper it follows):
 * ``gaussian``  Box-Muller transform of two 24-bit uniforms
 * ``sketch``    Alg. 1 step 2 / Section 2 "Step 1": Pi, sketches, column norms
 * ``srht``      the subsampled randomized Hadamard transform as Pi (Section 4, Spark)
+* ``sparse``    the sketch of matrices given as entries in any order (Section 1; Section 3 complexity)
 * ``sample``    Eq. (1) and Alg. 1 step 3: q, q-hat, Omega, weights
 * ``multinomial`` Appendix D "Sampling": row-wise multinomial draws of Omega
 * ``estimate``  Eq. (2): rescaled-JL estimates on Omega
@@ -25,4 +26,4 @@ Parity status: every function is pinned by a ``-m "not gpu"`` test except
 those marked "parity unpinned" in their docstring.
 """
 
-from . import philox, gaussian, sketch, sample, multinomial, estimate, waltmin, evaluate, solve, baselines, srht  # noqa: F401
+from . import philox, gaussian, sketch, sample, multinomial, estimate, waltmin, evaluate, solve, baselines, srht, sparse  # noqa: F401

@@ -34,11 +34,16 @@ def padded_size(d):
     return D
 
 
-def signs(seed, l0, l1):
-    """sigma_l for l in [l0, l1) as +1.0 / -1.0."""
-    l = np.arange(l0, l1, dtype=np.int64)
+def signs_at(seed, l):
+    """sigma_l for an array of indices l as +1.0 / -1.0."""
+    l = np.asarray(l, dtype=np.int64)
     w = stream_word_at(seed, TAG_SRHT_SIGN, np.zeros_like(l), l)
     return 1.0 - 2.0 * (w & 1).astype(np.float64)
+
+
+def signs(seed, l0, l1):
+    """sigma_l for l in [l0, l1) as +1.0 / -1.0."""
+    return signs_at(seed, np.arange(l0, l1, dtype=np.int64))
 
 
 def rows(seed, k, D):
@@ -63,6 +68,13 @@ def pi_block(seed, k, d, l0, l1):
     rho = rows(seed, k, padded_size(d))
     l = np.arange(l0, l1, dtype=np.int64)
     return hadamard_signs(rho, l) * signs(seed, l0, l1)[None, :] / np.sqrt(float(k))
+
+
+def pi_columns(seed, k, d, l):
+    """Pi[:, l] (k x len(l)) for an array of indices l < d in any order."""
+    l = np.asarray(l, dtype=np.int64)
+    rho = rows(seed, k, padded_size(d))
+    return hadamard_signs(rho, l) * signs_at(seed, l)[None, :] / np.sqrt(float(k))
 
 
 def sketch(A, B, seed, k, chunk=4096):

@@ -18,6 +18,9 @@ The shared latent Z makes A^T B approximately rank R plus noise.
 
 The random stream depends on the device (torch's CPU and GPU generators differ);
 tests build A and B once and hand the same tensors to both sides.
+
+Sparse inputs given as entries in arbitrary order (bag-of-words and URL-feature
+shapes) come from ``smp_inputs.sparse``.
 """
 
 import math
