@@ -1,7 +1,7 @@
 """Benchmark of the SMP-PCA hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload c3|c2|batch|serve] [--legs bf16,fp8,fp32,ab]
+                    [--workload c3|c2|batch|serve|sparse] [--legs bf16,fp8,fp32,ab]
                     [--no-c2] [--no-mix]
 
 A step is one smp_solve (Alg. 1 end to end: sketch pass, sampling, rescaled-JL
@@ -18,12 +18,15 @@ sketch ("srht", FP32), each with its spectral error; the roofline of the BF16 sk
 with its HBM rate; the d = 200,000, n = 2,000, k = 400 workload ("c2", BF16
 and FP32, and the paper's comparison methods LELA and SVD(A~^T B~) beside
 SMP-PCA with their errors); the one-coin-per-entry and the row-wise
-multinomial samplers ("sampler", n up to 100,000); the batching mix (512 jobs)
+multinomial samplers ("sampler", n up to 100,000); sparse inputs pushed as
+entries in random order ("sparse": the URL-reputation and NIPS-BW shapes,
+Gaussian FP32 / BF16 and SRHT sketches, with the accumulation kernel against
+its vector-ALU peak and the spectral errors); the batching mix (512 jobs)
 and the Poisson serving mix ("batch", "serve", solves/s and p50/p99 latency,
 BF16 vs FP32); and the FP64 CPU oracle's sketch pass timed on the host over a
 stated number of rows.
 
---workload c2|batch|serve prints the single-workload lines instead.
+--workload c2|batch|serve|sparse prints the single-workload lines instead.
 """
 
 import argparse
@@ -54,12 +57,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the CPU-oracle sketch sample (0: 200,000 at the large workload, all at c2)")
-    ap.add_argument("--workload", choices=("c3", "c2", "batch", "serve"), default="c3",
+    ap.add_argument("--workload", choices=("c3", "c2", "batch", "serve", "sparse"), default="c3",
                     help="c3: the large precision workload with every leg (default); c2: d = 200,000 only; "
-                         "batch: 512 jobs of the batching mix; serve: Poisson arrivals of the serving mix")
+                         "batch: 512 jobs of the batching mix; serve: Poisson arrivals of the serving mix; "
+                         "sparse: entry pushes of the sparse shapes only")
     ap.add_argument("--legs", default=",".join(LEGS), help="legs of the large workload to run (bf16,fp8,fp32,ab)")
     ap.add_argument("--no-c2", action="store_true", help="skip the d = 200,000 leg of the default line")
     ap.add_argument("--no-mix", action="store_true", help="skip the batching and serving legs of the default line")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the entry-push (sparse input) legs of the default line")
     ap.add_argument("--no-errors", action="store_true", help="skip the spectral errors (profiling runs)")
     ap.add_argument("--workers", type=int, default=4, help="server worker threads (batch, serve)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window of the serve workload")
@@ -446,6 +451,127 @@ def sampler_legs(api, ctx, dev, reps=5):
     return out
 
 
+# Entry-wise sketch (matrices given as entries in any order): the accumulation
+# kernel regenerates Pi per entry, so it is bound by the vector ALUs. Its peak
+# in entry-rows (one entry times one sketch row) per second: the chip issues
+# 256 CUs x 4 SIMDs x 16 lanes = 16,384 lane-instructions per clock at 2.4 GHz;
+# one Philox4x32-10 call with its Box-Muller transform and the four
+# multiply-adds takes 70 of them per lane (10 rounds of two 32x32->64-bit
+# products and two three-input XORs, 26 for the two Box-Muller pairs, 4 FMAs)
+# and serves 4 sketch rows; the SRHT takes 4 per entry-row (AND, popcount,
+# sign select, add).
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+SPARSE_PEAK_ENTRY_ROWS = {"gauss_fp32": VALU_LANE_OPS_PER_S * 4 / 70, "gauss_bf16": VALU_LANE_OPS_PER_S * 4 / 70,
+                          "srht": VALU_LANE_OPS_PER_S / 4}
+
+
+def sparse_legs(api, ctx, dev, seed, reps=5, errors=True):
+    """Entry pushes (smp_sketch_push_coo, entries in a random arrival order) of
+    the URL-reputation shape (Table 1: d = 792,145, two sets of 10,000
+    features, k = 2,000; ~20 M entries each) and the NIPS-BW shape (12,419
+    words x 750 + 750 papers, k = 400), then smp_solve_sketched, for the
+    Gaussian sketch in FP32 and BF16 and the SRHT; spectral errors against
+    A^T B formed by scipy.sparse on the host (outside the timed region)."""
+    import numpy as np
+    import scipy.sparse
+    import torch
+
+    from smp_inputs import sparse as spin
+    out = {}
+    for cname in ("s3_url", "s2_bow"):
+        c = spin.SPARSE_CONFIGS[cname]
+        A, B = spin.sparse_pair(c, seed)
+        d, n1, n2, k, r = c["d"], c["n1"], c["n2"], c["k"], c["r"]
+        dA = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in A]
+        dB = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in B]
+        nnz = len(A[0]) + len(B[0])
+        M = None
+        if errors:
+            SA = scipy.sparse.csr_matrix((A[2].astype(np.float64), (A[0], A[1])), shape=(d, n1))
+            SB = scipy.sparse.csr_matrix((B[2].astype(np.float64), (B[0], B[1])), shape=(d, n2))
+            M = torch.from_numpy((SA.T @ SB).toarray()).to(dev)
+            del SA, SB
+        row = {"workload": ("URL-reputation shape" if cname == "s3_url" else "NIPS-BW shape")
+               + f": d={d}, n1={n1}, n2={n2}, k={k}, r={r}, T={c['T']}, topic-model counts, entries in random order",
+               "nnz_a": len(A[0]), "nnz_b": len(B[0])}
+        At = torch.empty(n1, k, device=dev)
+        Bt = torch.empty(n2, k, device=dev)
+        na = torch.empty(n1, device=dev)
+        nb = torch.empty(n2, device=dev)
+        U = torch.empty(n1, r, dtype=torch.float64, device=dev)
+        V = torch.empty(n2, r, dtype=torch.float64, device=dev)
+        s = torch.empty(r, dtype=torch.float64, device=dev)
+        for name, kw in (("gauss_fp32", {}), ("gauss_bf16", {"prec": api.SMP_PREC_BF16}), ("srht", {"sketch": "srht"})):
+            p = api.make_params(d, n1, n2, k, r, T=c["T"], seed=seed, **kw)
+
+            def push_all():
+                st = ctx.smp_sketch_begin(p)
+                acc = 0.0
+                try:
+                    ctx.smp_sketch_push_coo(st, api.SMP_MAT_A, *dA)
+                    acc += ctx.smp_stage_times()["sketch"]
+                    ctx.smp_sketch_push_coo(st, api.SMP_MAT_B, *dB)
+                    acc += ctx.smp_stage_times()["sketch"]
+                    ctx.smp_sketch_end(st, At, Bt, na, nb)
+                    torch.cuda.synchronize()
+                finally:
+                    ctx.smp_sketch_free(st)
+                return acc
+
+            ctx.smp_set_timing(2)
+            push_all()
+            walls, kern = [], []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                kern.append(push_all())
+                walls.append(time.perf_counter() - t0)
+            ctx.smp_set_timing(0)
+            wall, kt = pct(walls, 50), pct(kern, 50) / 1e3
+            er = nnz * k / kt
+            peak = SPARSE_PEAK_ENTRY_ROWS[name]
+            leg = {"ms_per_sketch": round(wall * 1e3, 3), "accumulate_ms": round(kt * 1e3, 3),
+                   "entries_per_s": round(nnz / wall, 1),
+                   "roofline": {"bound": "alu", "achieved": round(er / 1e9, 2), "peak": round(peak / 1e9, 2),
+                                "unit": "G entry-rows/s", "frac": round(er / peak, 4),
+                                "kernel": "sp_sketch_kernel + sp_long_reduce_kernel of both pushes "
+                                          "(after the radix sort)", "kernel_ms": round(kt * 1e3, 3)}}
+            ctx.smp_solve_sketched(p, At, Bt, na, nb, U, V, s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.smp_solve_sketched(p, At, Bt, na, nb, U, V, s)
+            leg["solve_sketched_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+            if M is not None:
+                leg["spectral_error"] = spectral_error(M, U, s, V)
+            row[name] = leg
+        if M is not None and cname == "s2_bow":
+            sv = torch.linalg.svdvals(M)
+            row["optimal_error"] = float(sv[r] / sv[0])
+        out[cname] = row
+        del M, dA, dB, At, Bt
+        torch.cuda.empty_cache()
+    return out
+
+
+def main_sparse(args):
+    import torch
+
+    import smp_inputs
+    from paper_1610_06656_amd import api
+
+    dev = torch.device("cuda:0")
+    ctx = api.Context(0)
+    sp = sparse_legs(api, ctx, dev, smp_inputs.SEED_BASE, reps=max(1, args.steps), errors=not args.no_errors)
+    head = sp["s3_url"]["gauss_fp32"]
+    out = {"metric": "entries/s of the entry-wise sketch (both matrices) + ALU roofline of its accumulation kernel",
+           "value": head["entries_per_s"], "unit": "entries/s", "n_gpus": 1, "steps": max(1, args.steps),
+           "warmup": 1, "ms_per_step": head["ms_per_sketch"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": sp["s3_url"]["workload"]}, "roofline": head["roofline"]}
+    out.update(sp)
+    print(json.dumps(out), flush=True)
+
+
 def main_c2(args):
     import torch
 
@@ -498,6 +624,8 @@ def main():
         sys.exit(2)
     if args.workload in ("batch", "serve"):
         return main_mix(args)
+    if args.workload == "sparse":
+        return main_sparse(args)
     if args.workload == "c2":
         return main_c2(args)
     import torch
@@ -585,6 +713,8 @@ def main():
         out["c2"] = c2
         del A2, B2
         out["sampler"] = sampler_legs(api, ctx, dev)
+    if not args.no_sparse:
+        out["sparse"] = sparse_legs(api, ctx, dev, seed, errors=not args.no_errors)
     if not args.no_mix:
         import smp_inputs as si
         b = si.BATCH

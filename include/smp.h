@@ -184,6 +184,54 @@ smp_status smp_sketch_push(smp_ctx *ctx, smp_sketch_state *st, const float *A_ro
 smp_status smp_sketch_end(smp_ctx *ctx, smp_sketch_state *st, float *At, float *Bt, float *na2, float *nb2);
 void smp_sketch_free(smp_sketch_state *st);
 
+/* ---- entries in any order (Section 1: the entries of A and B may arrive in an
+ * arbitrary order, as in streaming logs; Section 3 "Computation Complexity":
+ * the sketch costs O(nnz(A) k + nnz(B) k)) ----------------------------------
+ * Add the entries (l, i, v) of A (which = SMP_MAT_A) or B (SMP_MAT_B) to a
+ * streaming state: A~[:, i] += v Pi[:, l], ||A_i||^2 += v^2, i.e. the state
+ * then holds the sketch of the matrix the entries describe (entries not
+ * given are zero). Every (l, i) may occur at most once over the whole stream
+ * of a matrix; a pair repeated inside one push is rejected, a pair repeated
+ * across pushes is the caller's error (its square would enter the norm
+ * twice). Entry pushes and dense row pushes (smp_sketch_push) may be mixed,
+ * each entry of the matrix given once in all.
+ *
+ * The result does not depend on the order of the entries in a push: they are
+ * grouped by (column, row) with a stable radix sort and every sum runs in a
+ * fixed order. Pi is the state's sketching matrix: the Gaussian Pi regenerated
+ * from the counter per entry (FP32 products; with SMP_PREC_BF16 both Pi and v
+ * rounded to bfloat16, exact products, FP32 sums) or, with SMP_SKETCH_SRHT, the
+ * SRHT's +-1/sqrt(k). SMP_PREC_FP8 states refuse entry pushes
+ * (SMP_ERR_INVALID_ARG: its scales need whole 32-row blocks of a column).
+ *
+ * COO: rows[e] (int64, in [0, d)), cols[e] (int32, in [0, n)), vals[e] (FP32),
+ * e < nnz, device arrays, any order. CSR: rows row0 .. row0 + nrows - 1 of the
+ * matrix (row0 + nrows <= d), row_ptr (nrows + 1 int64, row_ptr[0] = 0,
+ * row_ptr[nrows] = nnz, non-decreasing), cols and vals as for COO.
+ * 0 <= nnz < 2^31 per push; d * (n + 1) < 2^64.
+ *
+ * Each push synchronises the stream once, after validating the entries on
+ * the device: an index out of range, a repeated pair or an invalid row_ptr
+ * gives SMP_ERR_INVALID_ARG and leaves the state as it was. The state holds
+ * a device scratch of about 24 B per entry plus 16 B per column plus
+ * 8 k B per 512 entries (grown to the largest push; SMP_ERR_OUT_OF_MEMORY if
+ * that fails), released by smp_sketch_free. With SMP_B_IS_A only SMP_MAT_A is
+ * accepted. */
+enum { SMP_MAT_A = 0, SMP_MAT_B = 1 };
+smp_status smp_sketch_push_coo(smp_ctx *ctx, smp_sketch_state *st, int which, const int64_t *rows,
+                               const int32_t *cols, const float *vals, int64_t nnz);
+smp_status smp_sketch_push_csr(smp_ctx *ctx, smp_sketch_state *st, int which, int64_t row0, int64_t nrows,
+                               const int64_t *row_ptr, const int32_t *cols, const float *vals, int64_t nnz);
+
+/* Alg. 1 steps 3-5 (sampling, estimates, WAltMin) from sketches and squared
+ * norms already formed, e.g. by smp_sketch_end after streaming or entry
+ * pushes: the same outputs and errors as smp_solve, whose remaining stages it
+ * runs. At (n1 x k), Bt (n2 x k), na2 (n1), nb2 (n2) as smp_sketch writes
+ * them; with SMP_B_IS_A in p->flags, Bt and nb2 may be NULL (At and na2 are
+ * used). Synchronises the stream. */
+smp_status smp_solve_sketched(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt,
+                              const float *na2, const float *nb2, double *U, double *V, double *sigma);
+
 /* ---- a4: sampling (Eq. (1); Alg. 1 step 3; Alg. 2 steps 2-3) ---------------
  * From the FP32 squared norms na2 (n1) and nb2 (n2), draws Omega and writes
  * both listings and the weights into `om` (om->n1, n2, cap and the pointers
@@ -276,7 +324,8 @@ smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, c
 /* ---- stage timing ------------------------------------------------------------
  * With timing enabled, smp_solve (and smp_sketch) record HIP events on the
  * context's stream around each stage; smp_stage_times writes the durations (ms)
- * of the last call: [0] sketch kernel, [1] sketch reduction, [2] sampling,
+ * of the last call (an entry push records [0]: its accumulation kernels,
+ * after the sort): [0] sketch kernel, [1] sketch reduction, [2] sampling,
  * [3] estimate, [4] WAltMin (init + iterations + canonical form). Stages that
  * did not run report 0. n is the capacity of ms (up to 5 are written).
  * enable: 0 off, 1 every stage, 2 the sketch stage only (the others report 0);

@@ -27,6 +27,8 @@ SMP_OMEGA_SPLIT = 1
 SMP_B_IS_A = 1
 SMP_SAMPLE_MULTINOMIAL = 2
 SMP_SKETCH_SRHT = 4
+SMP_MAT_A = 0
+SMP_MAT_B = 1
 
 
 class SmpParams(ctypes.Structure):
@@ -80,6 +82,14 @@ EXPORTS = {
     "smp_sketch_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
     "smp_sketch_free": (None, [ctypes.c_void_p]),
+    "smp_sketch_push_coo": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "smp_sketch_push_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int64]),
+    "smp_solve_sketched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "smp_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(SmpOmega)]),
     "smp_estimate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_void_p,

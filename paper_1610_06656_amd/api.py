@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import SmpJobResult, SmpOmega, SmpParams, SmpServerStats
 from ._lib import SMP_B_IS_A, SMP_OMEGA_REUSE, SMP_OMEGA_SPLIT, SMP_PREC_BF16, SMP_PREC_FP32, SMP_PREC_FP8  # noqa: F401
-from ._lib import SMP_ERR_BUSY, SMP_ERR_NUMERIC  # noqa: F401
+from ._lib import SMP_ERR_BUSY, SMP_ERR_NUMERIC, SMP_MAT_A, SMP_MAT_B  # noqa: F401
 
 
 class SmpError(RuntimeError):
@@ -178,6 +178,30 @@ class Context:
 
     def smp_sketch_free(self, st):
         self.lib.smp_sketch_free(st)
+
+    def smp_sketch_push_coo(self, st, which, rows, cols, vals):
+        """Entries (rows[e], cols[e], vals[e]) of A (which = SMP_MAT_A) or B, in any order."""
+        nnz = rows.numel()
+        if cols.numel() != nnz or vals.numel() != nnz:
+            raise ValueError("rows, cols and vals differ in length")
+        self._check(self.lib.smp_sketch_push_coo(self.h, st, int(which), _ptr(rows, torch.int64, "rows"),
+                                                 _ptr(cols, torch.int32, "cols"), _ptr(vals, torch.float32, "vals"),
+                                                 nnz))
+
+    def smp_sketch_push_csr(self, st, which, row0, row_ptr, cols, vals):
+        """CSR rows row0 .. row0 + len(row_ptr) - 2 of A (which = SMP_MAT_A) or B."""
+        nnz = cols.numel()
+        if vals.numel() != nnz:
+            raise ValueError("cols and vals differ in length")
+        self._check(self.lib.smp_sketch_push_csr(self.h, st, int(which), int(row0), row_ptr.numel() - 1,
+                                                 _ptr(row_ptr, torch.int64, "row_ptr"), _ptr(cols, torch.int32, "cols"),
+                                                 _ptr(vals, torch.float32, "vals"), nnz))
+
+    def smp_solve_sketched(self, p, At, Bt, na2, nb2, U, V, sigma=None):
+        self._check(self.lib.smp_solve_sketched(self.h, ctypes.byref(p), _ptr(At, torch.float32, "At"),
+                                                _ptr(Bt, torch.float32, "Bt"), _ptr(na2, torch.float32, "na2"),
+                                                _ptr(nb2, torch.float32, "nb2"), _ptr(U, torch.float64, "U"),
+                                                _ptr(V, torch.float64, "V"), _ptr(sigma, torch.float64, "sigma")))
 
     def smp_sample(self, p, na2, nb2, om):
         o = om.struct()

@@ -20,7 +20,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsmp.so")
 ARCH = os.environ.get("SMP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "server.cpp", "sketch.hip", "sketch_bf16.hip", "sketch_fp8.hip", "sketch_srht.hip", "sample.hip", "sample_multi.hip",
+SOURCES = ["api.cpp", "server.cpp", "sketch.hip", "sketch_bf16.hip", "sketch_fp8.hip", "sketch_srht.hip", "sketch_sparse.hip", "sample.hip", "sample_multi.hip",
+           "sort_scan.hip",
            "estimate.hip", "waltmin.hip", "baselines.cpp"]
 
 COMMON = [

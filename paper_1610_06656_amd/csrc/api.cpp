@@ -165,6 +165,8 @@ struct smp_sketch_state {
   double *npart;
   void *pi = nullptr;    // stored-Pi scratch of the largest push so far
   size_t pi_bytes = 0;
+  void *sp = nullptr;    // entry-push scratch of the largest entry push so far
+  size_t sp_bytes = 0;
   bool ended;
 };
 
@@ -425,7 +427,79 @@ void smp_sketch_free(smp_sketch_state *st) {
   hipFree(st->part);
   hipFree(st->npart);
   if (st->pi) hipFree(st->pi);
+  if (st->sp) hipFree(st->sp);
   delete st;
+}
+
+// ---- entry pushes (f4): triples in any order ------------------------------------------
+
+static smp_status push_entries(smp_ctx *ctx, smp_sketch_state *st, int which, const smp::SparseIn &in) {
+  if (!ctx || !st) return fail(ctx, SMP_ERR_INVALID_ARG, "ctx or st is NULL");
+  if (st->ended) return fail(ctx, SMP_ERR_STATE, "push after end");
+  const smp_params &p = st->p;
+  const bool same = (p.flags & SMP_B_IS_A) != 0;
+  if (which != SMP_MAT_A && which != SMP_MAT_B) return fail(ctx, SMP_ERR_INVALID_ARG, "which must be SMP_MAT_A or SMP_MAT_B");
+  if (same && which == SMP_MAT_B) return fail(ctx, SMP_ERR_INVALID_ARG, "B is A (SMP_B_IS_A): push the entries as A");
+  if (p.prec == SMP_PREC_FP8)
+    return fail(ctx, SMP_ERR_INVALID_ARG,
+                "entry pushes need an FP32, BF16 or SRHT sketch (FP8 scales need whole 32-row blocks of a column)");
+  if (in.nnz < 0 || in.nnz > INT32_MAX) return fail(ctx, SMP_ERR_INVALID_ARG, "nnz must be in [0, 2^31)");
+  if (in.nnz == 0) return SMP_OK;
+  if (!in.cols || !in.vals || (!in.rows && !in.row_ptr)) return fail(ctx, SMP_ERR_INVALID_ARG, "an entry array is NULL");
+  const int64_t n = which == SMP_MAT_A ? p.n1 : p.n2;
+  if (!smp::sparse_key_fits(p.d, n)) return fail(ctx, SMP_ERR_INVALID_ARG, "d * (n + 1) must be below 2^64");
+  const size_t need = smp::sparse_ws_bytes(in.nnz, n, st->plan.kpad);
+  if (need > st->sp_bytes) {   // earlier pushes have finished with it (each push synchronises once)
+    SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (st->sp) hipFree(st->sp);
+    st->sp = nullptr;
+    st->sp_bytes = 0;
+    if (hipMalloc(&st->sp, need) != hipSuccess) {
+      hipGetLastError();
+      st->sp = nullptr;
+      return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "entry-push scratch allocation failed");
+    }
+    st->sp_bytes = need;
+  }
+  const int64_t off = which == SMP_MAT_B ? p.n1 : 0;
+  auto *res = reinterpret_cast<smp::SpStatus *>(ctx->host_pinned);
+  SMP_HIP(ctx, smp::sparse_prepare(st->plan, in, p.d, n, st->sp, res, ctx->stream));
+  if (res->bad_index) return fail(ctx, SMP_ERR_INVALID_ARG, "an entry's row or column index is out of range");
+  if (res->bad_ptr) return fail(ctx, SMP_ERR_INVALID_ARG, "row_ptr must start at 0, end at nnz and not decrease");
+  if (res->dup) return fail(ctx, SMP_ERR_INVALID_ARG, "an entry (row, column) occurs more than once in the push");
+  const smp::SpStatus prep = *res;
+  mark(ctx, kStSketch, false);   // stage [0]: the accumulation kernels of this push
+  SMP_HIP(ctx, smp::sparse_accumulate(st->plan, in, p.d, n, p.k, p.seed, st->part + off * st->plan.kpad,
+                                      st->npart + off, st->sp, prep, ctx->stream));
+  mark(ctx, kStSketch, true);
+  return SMP_OK;
+}
+
+smp_status smp_sketch_push_coo(smp_ctx *ctx, smp_sketch_state *st, int which, const int64_t *rows,
+                               const int32_t *cols, const float *vals, int64_t nnz) {
+  smp::SparseIn in;
+  in.rows = rows;
+  in.cols = cols;
+  in.vals = vals;
+  in.nnz = nnz;
+  if (nnz > 0 && !rows) return fail(ctx, SMP_ERR_INVALID_ARG, "rows is NULL");
+  return push_entries(ctx, st, which, in);
+}
+
+smp_status smp_sketch_push_csr(smp_ctx *ctx, smp_sketch_state *st, int which, int64_t row0, int64_t nrows,
+                               const int64_t *row_ptr, const int32_t *cols, const float *vals, int64_t nnz) {
+  if (st && (row0 < 0 || nrows < 0 || row0 + nrows > st->p.d))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "rows out of [0, d)");
+  if (nrows == 0 && nnz != 0) return fail(ctx, SMP_ERR_INVALID_ARG, "entries given for zero rows");
+  if (nnz > 0 && !row_ptr) return fail(ctx, SMP_ERR_INVALID_ARG, "row_ptr is NULL");
+  smp::SparseIn in;
+  in.row_ptr = row_ptr;
+  in.row0 = row0;
+  in.nrows = nrows;
+  in.cols = cols;
+  in.vals = vals;
+  in.nnz = nnz;
+  return push_entries(ctx, st, which, in);
 }
 
 smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
@@ -629,6 +703,10 @@ smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, c
   return waltmin_call(ctx, p, om, na2, U, V, sigma, nullptr);
 }
 
+static smp_status solve_after_sketch(smp_ctx *ctx, const smp_params &q, const float *At, const float *Bt,
+                                     const float *na2, const float *nb2, int64_t *rp, int64_t *cp, double *U,
+                                     double *V, double *sigma);
+
 smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,
                      double *U, double *V, double *sigma) {
   if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
@@ -656,7 +734,16 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
   int64_t *cp = take<int64_t>(hc, n2 + 2);
   s = smp_sketch(ctx, &q, A, lda, B, ldb, At, Bt, na2, nb2);
   if (s != SMP_OK) return s;
+  return solve_after_sketch(ctx, q, At, same ? At : Bt, na2, same ? na2 : nb2, rp, cp, U, V, sigma);
+}
 
+// Alg. 1 steps 3-5 from the sketches and norms: sampling, estimates, WAltMin.
+static smp_status solve_after_sketch(smp_ctx *ctx, const smp_params &q, const float *At, const float *Bt,
+                                     const float *na2, const float *nb2, int64_t *rp, int64_t *cp, double *U,
+                                     double *V, double *sigma) {
+  const int64_t n1 = q.n1, n2 = q.n2;
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s;
   // Omega: count first (one readback), then size the entry arrays exactly
   smp_omega om{};
   om.n1 = n1;
@@ -692,7 +779,7 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
   }
   mark(ctx, kStSample, true);
   mark(ctx, kStEstimate, false);
-  s = smp_estimate(ctx, &q, At, same ? At : Bt, na2, same ? na2 : nb2, &om);
+  s = smp_estimate(ctx, &q, At, Bt, na2, nb2, &om);
   if (s != SMP_OK) return s;
   mark(ctx, kStEstimate, true);
   mark(ctx, kStWaltmin, false);
@@ -706,6 +793,23 @@ smp_status smp_solve(smp_ctx *ctx, const smp_params *p, const float *A, int64_t 
   mark(ctx, kStWaltmin, true);
   SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return SMP_OK;
+}
+
+smp_status smp_solve_sketched(smp_ctx *ctx, const smp_params *p, const float *At, const float *Bt, const float *na2,
+                              const float *nb2, double *U, double *V, double *sigma) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string msg = check(p);
+  if (!msg.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, msg);
+  const bool same = (p->flags & SMP_B_IS_A) != 0;
+  if (!At || !na2 || (!same && (!Bt || !nb2))) return fail(ctx, SMP_ERR_INVALID_ARG, "a sketch or norm pointer is NULL");
+  if (!U || !V) return fail(ctx, SMP_ERR_INVALID_ARG, "U or V is NULL");
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.head, al((p->n1 + 2) * 8) + al((p->n2 + 2) * 8));
+  if (s != SMP_OK) return s;
+  char *hc = static_cast<char *>(b.head.p);
+  int64_t *rp = take<int64_t>(hc, p->n1 + 2);
+  int64_t *cp = take<int64_t>(hc, p->n2 + 2);
+  return solve_after_sketch(ctx, *p, At, same ? At : Bt, na2, same ? na2 : nb2, rp, cp, U, V, sigma);
 }
 
 // ---- comparison methods (Section 4) -------------------------------------------------

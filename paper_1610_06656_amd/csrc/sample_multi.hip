@@ -34,8 +34,6 @@ namespace smp {
 namespace {
 
 constexpr uint32_t kTagRowCount = 5, kTagDraw = 6;
-constexpr int kChunk = 4096;      // elements per workgroup of the scans
-constexpr int kTile = 1024;       // keys per workgroup of the radix sort (4 rounds of 256)
 
 inline unsigned blocks_for(int64_t items, int per) {
   return (unsigned)std::max<int64_t>(1, (items + per - 1) / per);
@@ -49,157 +47,6 @@ inline int bits_for(int64_t n) {   // bits of n - 1 (0 for n <= 1)
 
 __device__ __forceinline__ int64_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// ---- exclusive scans of int64 counts ---------------------------------------------
-// scan_large: chunk sums, a one-workgroup scan of the chunk sums, then each
-// chunk's own scan offset by its chunk's sum. Integer sums: exact in any order.
-
-__global__ __launch_bounds__(256) void chunk_sums_kernel(const int64_t *__restrict__ in, int64_t n,
-                                                         int64_t *__restrict__ sums) {
-  __shared__ int64_t red[256];
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
-  int64_t s = 0;
-#pragma unroll
-  for (int u = 0; u < kChunk / 256; ++u) {
-    const int64_t i = base + u * 256 + threadIdx.x;
-    s += i < n ? in[i] : 0;
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
-}
-
-// Exclusive scan of cnt[0..n) into ptr[0..n] by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void small_scan_kernel(const int64_t *__restrict__ cnt, int64_t n,
-                                                          int64_t *__restrict__ ptr) {
-  __shared__ int64_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = t * per, e = std::min<int64_t>(n, b + per);
-  int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += cnt[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int64_t add = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += add;
-    __syncthreads();
-  }
-  int64_t run = part[t] - s;
-  for (int64_t i = b; i < e; ++i) {
-    ptr[i] = run;
-    run += cnt[i];
-  }
-  if (t == 1023) ptr[n] = part[1023];
-}
-
-__global__ __launch_bounds__(256) void chunk_scan_kernel(const int64_t *__restrict__ in, int64_t n,
-                                                         const int64_t *__restrict__ off, int64_t *__restrict__ out) {
-  __shared__ int64_t part[256];
-  constexpr int PER = kChunk / 256;
-  const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)t * PER;
-  int64_t v[PER];
-  int64_t s = 0;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    v[u] = base + u < n ? in[base + u] : 0;
-    s += v[u];
-  }
-  part[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const int64_t add = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += add;
-    __syncthreads();
-  }
-  int64_t run = off[blockIdx.x] + part[t] - s;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    if (base + u < n) out[base + u] = run;
-    run += v[u];
-  }
-  if (blockIdx.x == gridDim.x - 1 && t == 255) out[n] = off[blockIdx.x] + part[255];
-}
-
-// ---- radix sort of uint64 keys (LSD, 8 bits per pass, stable) --------------------
-// n_dev: the number of keys on the device, clamped to nmax (the buffers'
-// size; the grid covers nmax).
-
-__global__ __launch_bounds__(256) void rs_hist_kernel(const uint64_t *__restrict__ keys, const int64_t *__restrict__ n_dev,
-                                                      int64_t nmax, int shift, int64_t ntiles,
-                                                      int64_t *__restrict__ hist) {
-  __shared__ int cnt[256];
-  const int64_t n = std::min<int64_t>(*n_dev, nmax);
-  cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-#pragma unroll
-  for (int r = 0; r < kTile / 256; ++r) {
-    const int64_t i = base + r * 256 + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(int)((keys[i] >> shift) & 255u)], 1);
-  }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];   // digit-major
-}
-
-// Each key goes to (offset of its digit in this tile) + (keys of the same
-// digit before it in the tile). Items are taken in index order (round r,
-// wave w, lane l -> index r*256 + 64 w + l); ranks inside a wave come from
-// eight ballots (the lanes whose digit matches bit by bit), per-wave digit
-// counts from the group's lowest lane, prefix over (round, wave) per digit.
-__global__ __launch_bounds__(256) void rs_scatter_kernel(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
-                                                         const int64_t *__restrict__ n_dev, int64_t nmax, int shift,
-                                                         int64_t ntiles, const int64_t *__restrict__ hoff) {
-  constexpr int R = kTile / 256;
-  __shared__ int cnt[R][4][256];
-  const int64_t n = std::min<int64_t>(*n_dev, nmax);
-  const int tid = threadIdx.x, wave = tid >> 6;
-  int *flat = &cnt[0][0][0];
-#pragma unroll
-  for (int u = 0; u < R * 4; ++u) flat[u * 256 + tid] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  uint64_t key[R];
-  int dg[R], rank[R];
-  bool val[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t i = base + r * 256 + tid;
-    val[r] = i < n;
-    key[r] = val[r] ? in[i] : 0;
-    dg[r] = (int)((key[r] >> shift) & 255u);
-    uint64_t mask = __ballot(val[r]);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (dg[r] >> b) & 1;
-      const uint64_t bal = __ballot(bit);
-      mask &= bit ? bal : ~bal;
-    }
-    rank[r] = (int)lanes_below(mask);
-    if (val[r] && rank[r] == 0) cnt[r][wave][dg[r]] = __popcll(mask);
-  }
-  __syncthreads();
-  int run = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int c = cnt[r][w][tid];
-      cnt[r][w][tid] = run;
-      run += c;
-    }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (val[r]) out[hoff[(int64_t)dg[r] * ntiles + blockIdx.x] + cnt[r][wave][dg[r]] + rank[r]] = key[r];
 }
 
 // ---- the sampler ------------------------------------------------------------------
@@ -393,16 +240,10 @@ int64_t mn_draw_bound(int64_t n1, double m) {
   return (int64_t)(m * (1.0 + 1e-9)) + n1 + 16;
 }
 
-static int64_t scan_chunks(int64_t n) { return (n + 1 + kChunk - 1) / kChunk; }
-
 size_t mn_ws_bytes(int64_t n1, int64_t n2, double m) {
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const int64_t dmax = mn_draw_bound(n1, m);
-  const int64_t ntiles = (dmax + kTile - 1) / kTile;
-  const int64_t hn = 256 * ntiles;
-  const int64_t sc = scan_chunks(std::max<int64_t>({hn, n1, n2}));
-  return al(n1 * 8) * 4 + al((n1 + 1) * 8) + al(n2 * 8) + al((n2 + 1) * 8) + 2 * al(dmax * 8) + al(hn * 8) +
-         al((hn + 1) * 8) + al(sc * 8) + al((sc + 1) * 8);
+  return al(n1 * 8) * 4 + al((n1 + 1) * 8) + al(n2 * 8) + al((n2 + 1) * 8) +
+         sort_ws_bytes(mn_draw_bound(n1, m), false, std::max(n1, n2));
 }
 
 void mn_ws_carve(void *base, int64_t n1, int64_t n2, double m, MnWs &w) {
@@ -414,9 +255,6 @@ void mn_ws_carve(void *base, int64_t n1, int64_t n2, double m, MnWs &w) {
     return p;
   };
   w.dmax = mn_draw_bound(n1, m);
-  w.ntiles = (w.dmax + kTile - 1) / kTile;
-  const int64_t hn = 256 * w.ntiles;
-  const int64_t sc = scan_chunks(std::max<int64_t>({hn, n1, n2}));
   w.a = static_cast<uint64_t *>(take(n1 * 8));
   w.tot = static_cast<uint64_t *>(take(n1 * 8));
   w.cnt = static_cast<int64_t *>(take(n1 * 8));
@@ -424,37 +262,7 @@ void mn_ws_carve(void *base, int64_t n1, int64_t n2, double m, MnWs &w) {
   w.doff = static_cast<int64_t *>(take((n1 + 1) * 8));
   w.b = static_cast<int64_t *>(take(n2 * 8));
   w.bptr = static_cast<int64_t *>(take((n2 + 1) * 8));
-  w.keys0 = static_cast<uint64_t *>(take(w.dmax * 8));
-  w.keys1 = static_cast<uint64_t *>(take(w.dmax * 8));
-  w.hist = static_cast<int64_t *>(take(hn * 8));
-  w.hoff = static_cast<int64_t *>(take((hn + 1) * 8));
-  w.csum = static_cast<int64_t *>(take(sc * 8));
-  w.coff = static_cast<int64_t *>(take((sc + 1) * 8));
-}
-
-// Exclusive scan of in[0..n) into out[0..n] (out[n] = total).
-static hipError_t scan_large(const MnWs &w, const int64_t *in, int64_t n, int64_t *out, hipStream_t st) {
-  const int64_t nb = std::max<int64_t>(1, (n + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(chunk_sums_kernel, dim3((unsigned)nb), dim3(256), 0, st, in, n, w.csum);
-  hipLaunchKernelGGL(small_scan_kernel, dim3(1), dim3(1024), 0, st, w.csum, nb, w.coff);
-  hipLaunchKernelGGL(chunk_scan_kernel, dim3((unsigned)nb), dim3(256), 0, st, in, n, w.coff, out);
-  return hipGetLastError();
-}
-
-// Sorts keys0[0..n) (n on the device, at most w.dmax) by their low `bits`
-// bits; returns the buffer holding the result (keys0 or keys1).
-static uint64_t *radix_sort(const MnWs &w, const int64_t *n_dev, int bits, hipStream_t st, hipError_t &err) {
-  uint64_t *src = w.keys0, *dst = w.keys1;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(rs_hist_kernel, dim3((unsigned)w.ntiles), dim3(256), 0, st, src, n_dev, w.dmax, shift, w.ntiles,
-                       w.hist);
-    if ((err = scan_large(w, w.hist, 256 * w.ntiles, w.hoff, st)) != hipSuccess) return src;
-    hipLaunchKernelGGL(rs_scatter_kernel, dim3((unsigned)w.ntiles), dim3(256), 0, st, src, dst, n_dev, w.dmax, shift,
-                       w.ntiles, w.hoff);
-    std::swap(src, dst);
-  }
-  err = hipGetLastError();
-  return src;
+  sort_ws_carve(c, w.dmax, false, std::max(n1, n2), w.srt);
 }
 
 hipError_t mn_count(const SampleWs &ws, const MnWs &w, int64_t n1, int64_t n2, double m, uint64_t seed,
@@ -462,18 +270,18 @@ hipError_t mn_count(const SampleWs &ws, const MnWs &w, int64_t n1, int64_t n2, d
   hipError_t e;
   hipLaunchKernelGGL(mn_weights_kernel, dim3(blocks_for(n1 + n2, 256)), dim3(256), 0, st, ws.alpha, ws.beta, n1, n2,
                      w.a, w.b);
-  if ((e = scan_large(w, w.b, n2, w.bptr, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.srt, w.b, n2, w.bptr, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(mn_counts_kernel, dim3(blocks_for(n1, 256)), dim3(256), 0, st, w.a, w.bptr, n1, n2, m, seed,
                      w.tot, w.cnt);
-  if ((e = scan_large(w, w.cnt, n1, w.doff, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.srt, w.cnt, n1, w.doff, st)) != hipSuccess) return e;
   const int bi = bits_for(n1), bj = bits_for(n2);
   hipLaunchKernelGGL(mn_draws_kernel, dim3(blocks_for(w.dmax, 256)), dim3(256), 0, st, w.a, w.bptr, w.tot, w.doff, n1,
-                     n2, w.dmax, seed, bj, w.keys0);
-  uint64_t *sorted = radix_sort(w, w.doff + n1, bi + bj, st, e);
-  if (e != hipSuccess) return e;
+                     n2, w.dmax, seed, bj, w.srt.keys0);
+  if ((e = radix_sort(w.srt, w.doff + n1, bi + bj, st)) != hipSuccess) return e;
+  const uint64_t *sorted = radix_result(w.srt, bi + bj);
   hipLaunchKernelGGL(mn_distinct_count_kernel, dim3(blocks_for(n1, 4)), dim3(256), 0, st, sorted, w.doff, n1, w.dmax,
                      w.dcnt);
-  return scan_large(w, w.dcnt, n1, row_ptr, st);
+  return scan_exclusive(w.srt, w.dcnt, n1, row_ptr, st);
 }
 
 hipError_t mn_fill(const SampleWs &ws, const MnWs &w, int64_t n1, int64_t n2, double m, uint64_t seed, int T,
@@ -481,16 +289,16 @@ hipError_t mn_fill(const SampleWs &ws, const MnWs &w, int64_t n1, int64_t n2, do
   (void)ws;
   const int bi = bits_for(n1), bj = bits_for(n2);
   // the draw keys sorted by mn_count sit where its passes left them
-  uint64_t *sorted = ((bi + bj + 7) / 8) % 2 == 0 ? w.keys0 : w.keys1;
+  const uint64_t *sorted = radix_result(w.srt, bi + bj);
   const uint64_t jmask = bj >= 64 ? ~0ull : ((1ull << bj) - 1);
   hipLaunchKernelGGL(mn_fill_rows_kernel, dim3(blocks_for(n1, 4)), dim3(256), 0, st, sorted, w.doff, w.a, w.b, n1,
                      w.dmax, m, seed, T, split, jmask, om.row_ptr, om.col_idx, om.w_csr, om.sub_csr);
   // CSC: sort the entries by (column, row); the draw keys are no longer needed
   hipLaunchKernelGGL(mn_csc_keys_kernel, dim3(blocks_for(om.cap, 256)), dim3(256), 0, st, om.row_ptr, om.col_idx, n1,
-                     om.cap, bi, w.keys0);
-  hipError_t e;
-  const uint64_t *cs = radix_sort(w, om.row_ptr + n1, bi + bj, st, e);
+                     om.cap, bi, w.srt.keys0);
+  const hipError_t e = radix_sort(w.srt, om.row_ptr + n1, bi + bj, st);
   if (e != hipSuccess) return e;
+  const uint64_t *cs = radix_result(w.srt, bi + bj);
   hipLaunchKernelGGL(mn_col_ptr_kernel, dim3(blocks_for(n2 + 1, 256)), dim3(256), 0, st, cs, om.row_ptr, n1, n2,
                      om.cap, bi, om.col_ptr);
   hipLaunchKernelGGL(mn_fill_cols_kernel, dim3(blocks_for(om.cap, 256)), dim3(256), 0, st, cs, om.row_ptr, om.col_idx,

@@ -34,7 +34,6 @@
 namespace smp {
 namespace {
 
-constexpr uint32_t kTagSrhtSign = 7, kTagSrhtRow = 8;
 constexpr int kC = 512;       // chunk rows
 constexpr int kW = 32;        // columns per workgroup
 constexpr int kXS = kW + 1;   // LDS row stride (floats)
@@ -50,12 +49,6 @@ struct SrhtArgs {
   float *part;
   double *npart;
 };
-
-__device__ __forceinline__ uint32_t word_at(uint64_t seed, uint32_t tag, uint64_t col) {
-  const u32x4 w = stream_call(seed, tag, 0ull, (uint32_t)(col >> 2));
-  const int u = (int)(col & 3);
-  return u == 0 ? w.x : (u == 1 ? w.y : (u == 2 ? w.z : w.w));
-}
 
 template <int ACC>
 __global__ __launch_bounds__(256) void srht_kernel(SrhtArgs g) {
@@ -84,7 +77,7 @@ __global__ __launch_bounds__(256) void srht_kernel(SrhtArgs g) {
   // this block's sketch rows: rho split into the chunk bits and the rest
   for (int u = tid; u < 8 * ACC; u += 256) {
     const int c = c0 + u;
-    const uint32_t r = c < g.k ? (word_at(g.seed, kTagSrhtRow, (uint64_t)c) & ((g.dbits >= 32 ? 0u : (1u << g.dbits)) - 1u))
+    const uint32_t r = c < g.k ? (stream_word(g.seed, kTagSrhtRow, 0ull, (uint64_t)c) & ((g.dbits >= 32 ? 0u : (1u << g.dbits)) - 1u))
                                : 0u;
     rho_lo[u] = (int)(r & (kC - 1));
     rho_hi[u] = (int)(r >> 9);

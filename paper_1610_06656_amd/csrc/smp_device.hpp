@@ -17,7 +17,10 @@
 
 namespace smp {
 
-enum : uint32_t { kTagPi = 1, kTagSample = 2, kTagSplit = 3, kTagInit = 4 };
+enum : uint32_t {
+  kTagPi = 1, kTagSample = 2, kTagSplit = 3, kTagInit = 4,
+  kTagSrhtSign = 7, kTagSrhtRow = 8   // the SRHT's signs sigma_l and Hadamard rows rho_c (row 0, column l or c)
+};
 
 struct u32x4 {
   uint32_t x, y, z, w;
@@ -49,6 +52,14 @@ __device__ __forceinline__ u32x4 philox10(u32x4 c, uint32_t k0, uint32_t k1) {
 __device__ __forceinline__ u32x4 stream_call(uint64_t seed, uint32_t tag, uint64_t row, uint32_t col_block) {
   return philox10(u32x4{col_block, (uint32_t)row, tag, (uint32_t)(row >> 32)}, (uint32_t)seed,
                   (uint32_t)(seed >> 32));
+}
+
+// The word the counter spec assigns to (row, col): lane col mod 4 of the call
+// (col / 4, row).
+__device__ __forceinline__ uint32_t stream_word(uint64_t seed, uint32_t tag, uint64_t row, uint64_t col) {
+  const u32x4 w = stream_call(seed, tag, row, (uint32_t)(col >> 2));
+  const int u = (int)(col & 3);
+  return u == 0 ? w.x : (u == 1 ? w.y : (u == 2 ? w.z : w.w));
 }
 
 // Box-Muller pair: u = ((a>>8)+1) 2^-24 in (0,1], phi = (b>>8) 2^-24 in [0,1),

@@ -121,20 +121,67 @@ hipError_t sample_count(const SampleWs &ws, int64_t n1, int64_t n2, double m, ui
 hipError_t sample_fill(const SampleWs &ws, int64_t n1, int64_t n2, double m, uint64_t seed, int T, int split,
                        const smp_omega &om, hipStream_t st);
 
+// ---- scans and radix sort (sort_scan.hip) --------------------------------------
+// Exclusive scans of int64 counts (out[0..n], out[n] = total) and a stable LSD
+// radix sort of uint64 keys, 8 bits per pass, with an optional uint32 payload.
+struct SortWs {
+  int64_t nmax = 0, ntiles = 0;                   // key capacity, radix tiles
+  int64_t scan_n = 0;                             // the longest scan the chunk buffers allow
+  uint64_t *keys0 = nullptr, *keys1 = nullptr;    // nmax each
+  uint32_t *vals0 = nullptr, *vals1 = nullptr;    // nmax each, or null: keys only
+  int64_t *hist = nullptr, *hoff = nullptr;       // 256 ntiles, + 1
+  int64_t *csum = nullptr, *coff = nullptr;       // scan chunk sums / offsets
+};
+int64_t radix_tiles(int64_t nmax);
+size_t sort_ws_bytes(int64_t nmax, bool payload, int64_t scan_n);
+void *sort_ws_carve(void *base, int64_t nmax, bool payload, int64_t scan_n, SortWs &w);   // returns the end
+hipError_t scan_exclusive(const SortWs &w, const int64_t *in, int64_t n, int64_t *out, hipStream_t st);
+// Sorts (keys0, vals0)[0 .. min(*n_dev, nmax)) by the low `bits` bits of the
+// keys. The result is in keys0/vals0 after an even number of 8-bit passes,
+// else in keys1/vals1 (radix_result).
+hipError_t radix_sort(const SortWs &w, const int64_t *n_dev, int bits, hipStream_t st);
+inline const uint64_t *radix_result(const SortWs &w, int bits) { return ((bits + 7) / 8) % 2 ? w.keys1 : w.keys0; }
+inline const uint32_t *radix_payload(const SortWs &w, int bits) { return ((bits + 7) / 8) % 2 ? w.vals1 : w.vals0; }
+
+// ---- entry-wise sketch (sketch_sparse.hip) ----------------------------------
+// One push of triples (l, i, v) of one matrix (COO: rows; CSR: row_ptr over
+// rows row0 .. row0 + nrows - 1) into the streaming state's partial slot 0.
+struct SparseIn {
+  const int64_t *rows = nullptr;      // COO row of each entry, or null
+  const int64_t *row_ptr = nullptr;   // CSR offsets (nrows + 1), or null
+  int64_t row0 = 0, nrows = 0;
+  const int32_t *cols = nullptr;
+  const float *vals = nullptr;
+  int64_t nnz = 0;
+};
+// Flags and counts of a push, read back once before anything is added.
+struct SpStatus {
+  int64_t nnz, nseg, nms, nlong;
+  int32_t bad_index, bad_ptr, dup, pad;
+};
+size_t sparse_ws_bytes(int64_t nnz, int64_t n, int kpad);
+bool sparse_key_fits(int64_t d, int64_t n);
+// Two phases of a push. prepare: keys, sort, column offsets and segments, then
+// one readback into *result (synchronises the stream); nothing is added to
+// the state. accumulate (only when prepare set no flag): the segment sketch
+// and the long-column reduction into part, npart (slot 0 of this matrix's
+// first column), with the same workspace.
+hipError_t sparse_prepare(const SketchPlan &pl, const SparseIn &in, int64_t d, int64_t n, void *ws, SpStatus *result,
+                          hipStream_t st);
+hipError_t sparse_accumulate(const SketchPlan &pl, const SparseIn &in, int64_t d, int64_t n, int k, uint64_t seed,
+                             float *part, double *npart, void *ws, const SpStatus &prep, hipStream_t st);
+
 // Row-wise multinomial sampler (Appendix D): device scratch and the two
 // passes (count: draws, sort, distinct entries per row -> row_ptr; fill: the
 // CSR entries, then the CSC listing).
 struct MnWs {
   int64_t dmax = 0;     // bound on the number of draws (buffers' size)
-  int64_t ntiles = 0;   // radix-sort tiles of dmax keys
   uint64_t *a = nullptr, *tot = nullptr;          // n1 each
   int64_t *cnt = nullptr, *dcnt = nullptr;        // n1 each
   int64_t *doff = nullptr;                        // n1 + 1
   int64_t *b = nullptr;                           // n2
   int64_t *bptr = nullptr;                        // n2 + 1
-  uint64_t *keys0 = nullptr, *keys1 = nullptr;    // dmax each
-  int64_t *hist = nullptr, *hoff = nullptr;       // 256 ntiles, + 1
-  int64_t *csum = nullptr, *coff = nullptr;       // scan chunk sums / offsets
+  SortWs srt;                                     // dmax draw keys, scans of up to max(n1, n2) counts
 };
 int64_t mn_draw_bound(int64_t n1, double m);
 size_t mn_ws_bytes(int64_t n1, int64_t n2, double m);
