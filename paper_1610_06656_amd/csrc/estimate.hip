@@ -15,10 +15,11 @@
 //    (v_mfma_f64_16x16x4f64, FP32 sketch entries widened exactly) and writes
 //    the estimates of the sampled entries of that block, found by binary
 //    search in each row's (column's) sorted listing;
-//  * gather (sparse grids): one wave per row of the CSR listing (resp. column
-//    of the CSC listing), a quarter-wave of 16 lanes per entry, lane u of the
-//    quarter summing components u, u+16, ...; the CSR and CSC kernels share
-//    the lane split and reduction tree.
+//  * gather (sparse grids): one wave per row of the CSR listing holds A~_i in
+//    registers and forms the dot products of its entries (two B~_j loads in
+//    flight, FP64 per-lane sums, a wave reduction); the CSC listing then
+//    copies each entry's value from the CSR listing (binary search for j in
+//    row i), so the two listings hold the same values.
 #include <algorithm>
 
 #include "smp_device.hpp"
@@ -45,16 +46,6 @@ __global__ void column_scale_kernel(const float *__restrict__ S, const float *__
   }
 }
 
-__device__ __forceinline__ double dot16(const float *__restrict__ a, const float *__restrict__ b, int k, int u) {
-  double acc = 0.0;
-  for (int c = u; c < k; c += 16) acc = fma((double)a[c], (double)b[c], acc);
-  acc += __shfl_xor(acc, 8, 64);
-  acc += __shfl_xor(acc, 4, 64);
-  acc += __shfl_xor(acc, 2, 64);
-  acc += __shfl_xor(acc, 1, 64);
-  return acc;
-}
-
 __device__ __forceinline__ double rescaled(double si, double sj, double ni, double nj, double dot) {
   const double den = ni * nj;
   if (!(den > 0.0)) return 0.0;
@@ -62,42 +53,101 @@ __device__ __forceinline__ double rescaled(double si, double sj, double ni, doub
   return (si * sj) * cosv;
 }
 
-// Entries of row i: (i, idx[e]) for e in [ptr[i], ptr[i+1]).
-__global__ void estimate_rows_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                     const float *__restrict__ At, const float *__restrict__ Bt,
-                                     const double *__restrict__ na, const double *__restrict__ nb,
-                                     const double *__restrict__ sa, const double *__restrict__ sb, int64_t n_out,
-                                     int k, double *__restrict__ mt) {
-  const int lane = threadIdx.x & 63;
-  const int quarter = lane >> 4, u = lane & 15;
-  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= n_out) return;
-  const int64_t e0 = ptr[i], e1 = ptr[i + 1];
-  const float *a = At + i * k;
-  // each quarter-wave walks its own entries; the shuffles stay inside the quarter
-  for (int64_t e = e0 + quarter; e < e1; e += 4) {
-    const int64_t j = idx[e];
-    const double d = dot16(a, Bt + j * (int64_t)k, k, u);
-    if (u == 0) mt[e] = rescaled(sa[i], sb[j], na[i], nb[j], d);
+// A sketch column of k FP32 values spread over a wave: lane t holds 4 M values,
+// component 256 m + 4 t + q (VEC: one 16-byte load per m, k a multiple of 4)
+// or 64 (4 m + q) + t (scalar loads); components >= k read as 0.
+template <int M, bool VEC>
+__device__ __forceinline__ void load_col(const float *__restrict__ src, int k, int lane, float (&v)[4 * M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    if (VEC) {
+      const int c = 256 * m + 4 * lane;
+      const float4 x = c < k ? *reinterpret_cast<const float4 *>(src + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[4 * m + 0] = x.x;
+      v[4 * m + 1] = x.y;
+      v[4 * m + 2] = x.z;
+      v[4 * m + 3] = x.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 64 * (4 * m + q) + lane;
+        v[4 * m + q] = c < k ? src[c] : 0.0f;
+      }
+    }
   }
 }
 
-// Entries of column j: (idx[e], j) for e in [ptr[j], ptr[j+1]).
-__global__ void estimate_cols_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                     const float *__restrict__ At, const float *__restrict__ Bt,
-                                     const double *__restrict__ na, const double *__restrict__ nb,
-                                     const double *__restrict__ sa, const double *__restrict__ sb, int64_t n_out,
-                                     int k, double *__restrict__ mt) {
+template <int M>
+__device__ __forceinline__ double dot_wave(const float (&a)[4 * M], const float (&b)[4 * M]) {
+  double acc = 0.0;
+#pragma unroll
+  for (int x = 0; x < 4 * M; ++x) acc = fma((double)a[x], (double)b[x], acc);
+  return wave_sum(acc);
+}
+
+// Gather path, one wave per row i of the CSR listing: A~_i stays in registers,
+// the B~_j of two entries are loaded together (one for k > 2048), each dot
+// product is a per-lane
+// FP64 sum and a wave reduction (a fixed order).
+template <int M, bool VEC>
+__global__ __launch_bounds__(256) void estimate_rows_kernel(const int64_t *__restrict__ ptr,
+                                                            const int32_t *__restrict__ idx,
+                                                            const float *__restrict__ At, const float *__restrict__ Bt,
+                                                            const double *__restrict__ na,
+                                                            const double *__restrict__ nb,
+                                                            const double *__restrict__ sa,
+                                                            const double *__restrict__ sb, int64_t n1, int k,
+                                                            double *__restrict__ mt) {
   const int lane = threadIdx.x & 63;
-  const int quarter = lane >> 4, u = lane & 15;
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= n1) return;
+  const int64_t e0 = ptr[i], e1 = ptr[i + 1];
+  if (e0 >= e1) return;
+  float a[4 * M];
+  load_col<M, VEC>(At + i * (int64_t)k, k, lane, a);
+  const double si = sa[i], ni = na[i];
+  int64_t e = e0;
+  for (; M <= 8 && e + 1 < e1; e += 2) {   // k > 2048: one entry at a time (registers)
+    const int64_t j0 = idx[e], j1 = idx[e + 1];
+    float b0[4 * M], b1[4 * M];
+    load_col<M, VEC>(Bt + j0 * (int64_t)k, k, lane, b0);
+    load_col<M, VEC>(Bt + j1 * (int64_t)k, k, lane, b1);
+    const double d0 = dot_wave<M>(a, b0), d1 = dot_wave<M>(a, b1);
+    if (lane == 0) {
+      mt[e] = rescaled(si, sb[j0], ni, nb[j0], d0);
+      mt[e + 1] = rescaled(si, sb[j1], ni, nb[j1], d1);
+    }
+  }
+  for (; e < e1; ++e) {
+    const int64_t j0 = idx[e];
+    float b0[4 * M];
+    load_col<M, VEC>(Bt + j0 * (int64_t)k, k, lane, b0);
+    const double d0 = dot_wave<M>(a, b0);
+    if (lane == 0) mt[e] = rescaled(si, sb[j0], ni, nb[j0], d0);
+  }
+}
+
+// The CSC listing's estimates from the CSR listing: one wave per column j, a
+// lane per entry (i, j), whose CSR position is found by binary search for j
+// in row i's sorted columns.
+__global__ __launch_bounds__(256) void estimate_csc_copy_kernel(const int64_t *__restrict__ cp,
+                                                                const int32_t *__restrict__ ri,
+                                                                const int64_t *__restrict__ rp,
+                                                                const int32_t *__restrict__ ci, int64_t n2,
+                                                                const double *__restrict__ mt_csr,
+                                                                double *__restrict__ mt_csc) {
+  const int lane = threadIdx.x & 63;
   const int64_t j = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (j >= n_out) return;
-  const int64_t e0 = ptr[j], e1 = ptr[j + 1];
-  const float *b = Bt + j * k;
-  for (int64_t e = e0 + quarter; e < e1; e += 4) {
-    const int64_t i = idx[e];
-    const double d = dot16(At + i * (int64_t)k, b, k, u);
-    if (u == 0) mt[e] = rescaled(sa[i], sb[j], na[i], nb[j], d);
+  if (j >= n2) return;
+  for (int64_t e = cp[j] + lane; e < cp[j + 1]; e += 64) {
+    const int64_t i = ri[e];
+    int64_t lo = rp[i], hi = rp[i + 1] - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ci[mid] < j) lo = mid + 1;
+      else hi = mid;
+    }
+    mt_csc[e] = mt_csr[lo];
   }
 }
 
@@ -296,10 +346,27 @@ hipError_t estimate_run(const float *At, const float *Bt, const float *na2, cons
     hipLaunchKernelGGL(estimate_tiles_kernel, grid, dim3(256), 0, st, At, Bt, n1, n2, k, na, nb, sa, sb, om.row_ptr,
                        om.col_idx, om.col_ptr, om.row_idx, om.mt_csr, om.mt_csc);
   } else if (om.nnz > 0) {
-    hipLaunchKernelGGL(estimate_rows_kernel, dim3(waves_grid(n1)), dim3(256), 0, st, om.row_ptr, om.col_idx, At, Bt,
-                       na, nb, sa, sb, n1, k, om.mt_csr);
-    hipLaunchKernelGGL(estimate_cols_kernel, dim3(waves_grid(n2)), dim3(256), 0, st, om.col_ptr, om.row_idx, At, Bt,
-                       na, nb, sa, sb, n2, k, om.mt_csc);
+    const int M = k <= 256 ? 1 : k <= 512 ? 2 : k <= 1024 ? 4 : k <= 2048 ? 8 : 16;
+    const bool vec = k % 4 == 0;
+    const dim3 g(waves_grid(n1)), b(256);
+#define SMP_ROWS(MM, VV)                                                                                            \
+  hipLaunchKernelGGL((estimate_rows_kernel<MM, VV>), g, b, 0, st, om.row_ptr, om.col_idx, At, Bt, na, nb, sa, sb, \
+                     n1, k, om.mt_csr)
+    switch (M * 2 + (vec ? 1 : 0)) {
+      case 3: SMP_ROWS(1, true); break;
+      case 2: SMP_ROWS(1, false); break;
+      case 5: SMP_ROWS(2, true); break;
+      case 4: SMP_ROWS(2, false); break;
+      case 9: SMP_ROWS(4, true); break;
+      case 8: SMP_ROWS(4, false); break;
+      case 17: SMP_ROWS(8, true); break;
+      case 16: SMP_ROWS(8, false); break;
+      case 33: SMP_ROWS(16, true); break;
+      default: SMP_ROWS(16, false); break;
+    }
+#undef SMP_ROWS
+    hipLaunchKernelGGL(estimate_csc_copy_kernel, dim3(waves_grid(n2)), dim3(256), 0, st, om.col_ptr, om.row_idx,
+                       om.row_ptr, om.col_idx, n2, om.mt_csr, om.mt_csc);
   }
   return hipGetLastError();
 }
