@@ -496,6 +496,7 @@ __device__ __forceinline__ void finish_rows_if(const Row<NV> (&x)[8], int64_t ro
 template <int MT, int NV, int G, int W, int D, bool VEC, bool CLAMP, bool NORM>
 __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &w, int64_t col, int i0, int mv,
                                                  v4u *L, v4f (&acc)[MT][NV], float (&ksum)[NV], float (&kcmp)[NV]) {
+  static_assert(D >= 2, "step t + 1 lands in another LDS buffer than the one step t reads");
   constexpr int CPW = (MT + W - 1) / W;
   constexpr int LT = CPW * W;   // m-tile slots per LDS buffer
   const int tid = threadIdx.x;
@@ -602,9 +603,14 @@ struct ShapeS {
 };
 
 ShapeS *shapes_stored(int &count) {
-  static ShapeS tabs[] = {{2, 8, 2, 13, {}, {}, {}}};
+  // (nv 2, 8 waves, up to 13 m-tiles): two waves per SIMD, 256 columns;
+  // (nv 4, 4 waves, 13 to 16 m-tiles): one wave per SIMD with its accumulators
+  // in the AGPRs, 256 columns x 256 sketch rows, used for k >= 640 (fewer
+  // sketch-row chunks: at k = 1,024, 4 instead of 5 reads of every data tile)
+  static ShapeS tabs[] = {{2, 8, 2, 13, {}, {}, {}}, {4, 4, 2, 16, {}, {}, {}}};
   static const bool init = [] {
     KTabS<2, 2, 8, 2, 13, 0>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts);
+    KTabS<4, 4, 4, 2, 16, 12>::fill(tabs[1].t, tabs[1].tc, tabs[1].ts);
     return true;
   }();
   (void)init;
@@ -670,6 +676,11 @@ static SketchPlan sketch_plan_bf16_regen(int k) {
 // the regenerating pass above.
 SketchPlan sketch_plan_bf16(int k) {
   int nv = 2, waves = 8, depth = 2, cap = 13;
+  if ((k + 15) / 16 >= 40) {   // 4 % faster at d = 10^6, n = 8,192, k = 1,024 (22.8 -> 21.7 ms)
+    nv = 4;
+    waves = 4;
+    cap = 16;
+  }
   if (const char *e = getenv("SMP_SKETCH_BF16_STORED")) {
     int env[4] = {0, 0, 0, 0};
     const int got = sscanf(e, "%d,%d,%d,%d", &env[0], &env[1], &env[2], &env[3]);

@@ -73,6 +73,8 @@ SKETCH_CASES = {
     "ragged": dict(d=1037, n1=77, n2=131, k=37),
     "k400_tiles": dict(d=20000, n1=300, n2=1100, k=400),
     "k1024_chunks": dict(d=4096, n1=129, n2=64, k=1024),
+    "k700_wide_chunks": dict(d=3000, n1=300, n2=77, k=700),
+    "k2000_wide_chunks": dict(d=1500, n1=90, n2=41, k=2000),
     "tiny": dict(d=3, n1=1, n2=5, k=1),
     "one_block_tail": dict(d=130, n1=513, n2=2, k=81),
 }
