@@ -453,14 +453,16 @@ def sampler_legs(api, ctx, dev, reps=5):
 
 # Entry-wise sketch (matrices given as entries in any order): the accumulation
 # kernel regenerates Pi per entry, so it is bound by the vector ALUs. Its peak
-# in entry-rows (one entry times one sketch row) per second: the chip issues
-# 256 CUs x 4 SIMDs x 16 lanes = 16,384 lane-instructions per clock at 2.4 GHz;
+# in entry-rows (one entry times one sketch row) per second comes from the
+# published FP32 vector rate, 157.3 TFLOP/s = 78.65 T lane-operations per
+# second (an FMA counted once; 128 per clock per CU at 2.4 GHz on 256 CUs):
 # one Philox4x32-10 call with its Box-Muller transform and the four
 # multiply-adds takes 70 of them per lane (10 rounds of two 32x32->64-bit
 # products and two three-input XORs, 26 for the two Box-Muller pairs, 4 FMAs)
 # and serves 4 sketch rows; the SRHT takes 4 per entry-row (AND, popcount,
-# sign select, add).
-VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# sign select, add). Transcendentals and 64-bit products issue slower than
+# that rate, so this peak is an upper bound for the instruction mix.
+VALU_LANE_OPS_PER_S = 157.3e12 / 2
 SPARSE_PEAK_ENTRY_ROWS = {"gauss_fp32": VALU_LANE_OPS_PER_S * 4 / 70, "gauss_bf16": VALU_LANE_OPS_PER_S * 4 / 70,
                           "srht": VALU_LANE_OPS_PER_S / 4}
 

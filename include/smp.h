@@ -212,10 +212,10 @@ void smp_sketch_free(smp_sketch_state *st);
  *
  * Each push synchronises the stream once, after validating the entries on
  * the device: an index out of range, a repeated pair or an invalid row_ptr
- * gives SMP_ERR_INVALID_ARG and leaves the state as it was. The state holds
- * a device scratch of about 24 B per entry plus 16 B per column plus
- * 8 k B per 512 entries (grown to the largest push; SMP_ERR_OUT_OF_MEMORY if
- * that fails), released by smp_sketch_free. With SMP_B_IS_A only SMP_MAT_A is
+ * gives SMP_ERR_INVALID_ARG and leaves the state as it was. The context holds
+ * a device scratch of about 28 B per entry plus 64 B per column plus
+ * 4 k B per 256 entries (grown to the largest push; SMP_ERR_OUT_OF_MEMORY if
+ * that fails), released by smp_destroy. With SMP_B_IS_A only SMP_MAT_A is
  * accepted. */
 enum { SMP_MAT_A = 0, SMP_MAT_B = 1 };
 smp_status smp_sketch_push_coo(smp_ctx *ctx, smp_sketch_state *st, int which, const int64_t *rows,

@@ -165,8 +165,6 @@ struct smp_sketch_state {
   double *npart;
   void *pi = nullptr;    // stored-Pi scratch of the largest push so far
   size_t pi_bytes = 0;
-  void *sp = nullptr;    // entry-push scratch of the largest entry push so far
-  size_t sp_bytes = 0;
   bool ended;
 };
 
@@ -205,7 +203,7 @@ static void *scratch_for(int device) {
 }
 
 struct smp_ctx_bufs {
-  Buf sketch, samplews, head, omega, est, wm, mn, base;
+  Buf sketch, samplews, head, omega, est, wm, mn, base, sparse;
 };
 
 namespace {
@@ -268,7 +266,7 @@ void smp_destroy(smp_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
   if (b) {
-    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base})
+    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base, &b->sparse})
       if (x->p) hipFree(x->p);
     delete b;
   }
@@ -427,7 +425,6 @@ void smp_sketch_free(smp_sketch_state *st) {
   hipFree(st->part);
   hipFree(st->npart);
   if (st->pi) hipFree(st->pi);
-  if (st->sp) hipFree(st->sp);
   delete st;
 }
 
@@ -448,29 +445,20 @@ static smp_status push_entries(smp_ctx *ctx, smp_sketch_state *st, int which, co
   if (!in.cols || !in.vals || (!in.rows && !in.row_ptr)) return fail(ctx, SMP_ERR_INVALID_ARG, "an entry array is NULL");
   const int64_t n = which == SMP_MAT_A ? p.n1 : p.n2;
   if (!smp::sparse_key_fits(p.d, n)) return fail(ctx, SMP_ERR_INVALID_ARG, "d * (n + 1) must be below 2^64");
-  const size_t need = smp::sparse_ws_bytes(in.nnz, n, st->plan.kpad);
-  if (need > st->sp_bytes) {   // earlier pushes have finished with it (each push synchronises once)
-    SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (st->sp) hipFree(st->sp);
-    st->sp = nullptr;
-    st->sp_bytes = 0;
-    if (hipMalloc(&st->sp, need) != hipSuccess) {
-      hipGetLastError();
-      st->sp = nullptr;
-      return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "entry-push scratch allocation failed");
-    }
-    st->sp_bytes = need;
-  }
+  // the context's scratch, grown to the largest push (pushes run in stream order)
+  smp_ctx_bufs &b = bufs(ctx);
+  const smp_status s = ensure(ctx, b.sparse, smp::sparse_ws_bytes(in.nnz, n, st->plan.kpad));
+  if (s != SMP_OK) return s;
   const int64_t off = which == SMP_MAT_B ? p.n1 : 0;
   auto *res = reinterpret_cast<smp::SpStatus *>(ctx->host_pinned);
-  SMP_HIP(ctx, smp::sparse_prepare(st->plan, in, p.d, n, st->sp, res, ctx->stream));
+  SMP_HIP(ctx, smp::sparse_prepare(st->plan, in, p.d, n, b.sparse.p, res, ctx->stream));
   if (res->bad_index) return fail(ctx, SMP_ERR_INVALID_ARG, "an entry's row or column index is out of range");
   if (res->bad_ptr) return fail(ctx, SMP_ERR_INVALID_ARG, "row_ptr must start at 0, end at nnz and not decrease");
   if (res->dup) return fail(ctx, SMP_ERR_INVALID_ARG, "an entry (row, column) occurs more than once in the push");
   const smp::SpStatus prep = *res;
   mark(ctx, kStSketch, false);   // stage [0]: the accumulation kernels of this push
   SMP_HIP(ctx, smp::sparse_accumulate(st->plan, in, p.d, n, p.k, p.seed, st->part + off * st->plan.kpad,
-                                      st->npart + off, st->sp, prep, ctx->stream));
+                                      st->npart + off, b.sparse.p, prep, ctx->stream));
   mark(ctx, kStSketch, true);
   return SMP_OK;
 }

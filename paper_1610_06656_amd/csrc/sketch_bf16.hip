@@ -11,7 +11,7 @@
 // Stored-Pi pass (the default). Pi is drawn once per push (one Philox call per
 // four sketch rows of a data row) into a scratch buffer in the MFMA A-operand
 // order, and the pass is a split-K GEMM over it: each workgroup (8 waves, two
-// per SIMD) owns 16*8*NV = 256 columns, a chunk of up to 13 m-tiles and one of
+// per SIMD) owns 16*8*NV = 256 columns, a chunk of up to 16 m-tiles and one of
 // S row splits. Per K step of 32 rows every lane loads its 8 rows x NV
 // columns and each wave copies its share of the chunk's 1 KiB Pi fragments
 // into an LDS buffer, D steps ahead of use; the wave then multiplies all
@@ -603,14 +603,11 @@ struct ShapeS {
 };
 
 ShapeS *shapes_stored(int &count) {
-  // (nv 2, 8 waves, up to 13 m-tiles): two waves per SIMD, 256 columns;
-  // (nv 4, 4 waves, 13 to 16 m-tiles): one wave per SIMD with its accumulators
-  // in the AGPRs, 256 columns x 256 sketch rows, used for k >= 640 (fewer
-  // sketch-row chunks: at k = 1,024, 4 instead of 5 reads of every data tile)
-  static ShapeS tabs[] = {{2, 8, 2, 13, {}, {}, {}}, {4, 4, 2, 16, {}, {}, {}}};
+  // nv 2, 8 waves (two per SIMD), up to 16 m-tiles: 256 columns x 256 sketch
+  // rows, 242 VGPRs at 16 m-tiles
+  static ShapeS tabs[] = {{2, 8, 2, 16, {}, {}, {}}};
   static const bool init = [] {
-    KTabS<2, 2, 8, 2, 13, 0>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts);
-    KTabS<4, 4, 4, 2, 16, 12>::fill(tabs[1].t, tabs[1].tc, tabs[1].ts);
+    KTabS<2, 2, 8, 2, 16, 0>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts);
     return true;
   }();
   (void)init;
@@ -675,12 +672,11 @@ static SketchPlan sketch_plan_bf16_regen(int k) {
 // SMP_SKETCH_BF16_STORED="nv,waves,depth,cap" picks the shape, "0" selects
 // the regenerating pass above.
 SketchPlan sketch_plan_bf16(int k) {
-  int nv = 2, waves = 8, depth = 2, cap = 13;
-  if ((k + 15) / 16 >= 40) {   // 4 % faster at d = 10^6, n = 8,192, k = 1,024 (22.8 -> 21.7 ms)
-    nv = 4;
-    waves = 4;
-    cap = 16;
-  }
+  // up to 16 m-tiles per chunk: at k = 1,024 every data tile is read by 4
+  // chunks instead of 5 with 13 (22.8 -> 19.8 ms at d = 10^6, n = 8,192);
+  // one wave per SIMD with the accumulators in AGPRs (nv 4, 4 waves) was
+  // slower (21.7 ms): it spills and leaves less latency hidden
+  int nv = 2, waves = 8, depth = 2, cap = 16;
   if (const char *e = getenv("SMP_SKETCH_BF16_STORED")) {
     int env[4] = {0, 0, 0, 0};
     const int got = sscanf(e, "%d,%d,%d,%d", &env[0], &env[1], &env[2], &env[3]);
