@@ -310,11 +310,14 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes) {
   if (!m.empty()) return fail(nullptr, SMP_ERR_INVALID_ARG, m);
   if (!bytes) return fail(nullptr, SMP_ERR_INVALID_ARG, "bytes is NULL");
   const SketchPlan pl = plan_for(p);
-  const int S = choose_splits(pl, p->d, p->n1, p->n2);
   const int64_t nt = p->n1 + p->n2, k = p->k;
   size_t s = 0;
-  const int slots = smp::sketch_slots_total(pl, S);
-  s += al((size_t)slots * nt * pl.kpad * 4) + al((size_t)slots * nt * 8);   // sketch partials
+  // sketch partials, for B given and for B = A (smp_solve treats B == A as SMP_B_IS_A)
+  for (const int64_t n2 : {p->n2, int64_t(0)}) {
+    if (n2 == 0 && p->n1 != p->n2) continue;
+    const int slots = smp::sketch_slots_total(pl, choose_splits(pl, p->d, p->n1, n2));
+    s = std::max(s, al((size_t)slots * (p->n1 + n2) * pl.kpad * 4) + al((size_t)slots * (p->n1 + n2) * 8));
+  }
   s += al(smp::sketch_pi_bytes(pl, p->d));                                  // stored-Pi window of the one-shot pass
   s += al(nt * k * 4) + al(nt * 4);                                       // sketches + norms
   s += al(64) + al(nt * 8) + al((nt / 256 + 4) * 8) + al((nt + 2) * 8);   // sampling
@@ -350,7 +353,7 @@ smp_status smp_sketch_begin(smp_ctx *ctx, const smp_params *p, smp_sketch_state 
   s->ctx = ctx;
   s->p = *p;
   s->plan = plan_for(p);
-  s->S = choose_splits(s->plan, p->d, p->n1, p->n2);
+  s->S = choose_splits(s->plan, p->d, p->n1, (p->flags & SMP_B_IS_A) ? 0 : p->n2);
   const int64_t n2 = (p->flags & SMP_B_IS_A) ? 0 : p->n2;
   const int64_t nt = p->n1 + n2;
   const int slots = smp::sketch_slots_total(s->plan, s->S);
@@ -501,8 +504,8 @@ smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t
   if (!At || !na2 || (!same && (!Bt || !nb2))) return fail(ctx, SMP_ERR_INVALID_ARG, "output pointer is NULL");
   // the one-shot pass keeps its partials in the context's workspace
   const SketchPlan pl = plan_for(p);
-  const int S = choose_splits(pl, p->d, p->n1, p->n2);
   const int64_t n2 = same ? 0 : p->n2;
+  const int S = choose_splits(pl, p->d, p->n1, n2);   // B = A: only A's column tiles run
   const int64_t nt = p->n1 + n2;
   const int slots = smp::sketch_slots_total(pl, S);
   const size_t pb = al((size_t)slots * nt * pl.kpad * 4), nb = al((size_t)slots * nt * 8);
