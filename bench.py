@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-c2", action="store_true", help="skip the d = 200,000 leg of the default line")
     ap.add_argument("--no-mix", action="store_true", help="skip the batching and serving legs of the default line")
     ap.add_argument("--no-sparse", action="store_true", help="skip the entry-push (sparse input) legs of the default line")
+    ap.add_argument("--tune", action="store_true",
+                    help="run smp_tune_sketch for the BF16, FP8 and A = B shapes of the large workload before the "
+                         "timed legs (the legs then use the tuned launch shapes)")
     ap.add_argument("--no-errors", action="store_true", help="skip the spectral errors (profiling runs)")
     ap.add_argument("--workers", type=int, default=4, help="server worker threads (batch, serve)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window of the serve workload")
@@ -646,6 +649,16 @@ def main():
     ctx = api.Context(0)
     prec_of = {"bf16": api.SMP_PREC_BF16, "fp8": api.SMP_PREC_FP8, "fp32": api.SMP_PREC_FP32, "ab": api.SMP_PREC_BF16,
                "srht": api.SMP_PREC_FP32}
+    tune = {}
+    if args.tune:   # launch shapes measured by smp_tune_sketch before any timed region; the legs then use them
+        for name in legs_wanted:
+            if name in ("bf16", "fp8", "ab"):
+                p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], c["r"], T=c["T"], seed=seed,
+                                    prec=prec_of[name], b_is_a=(name == "ab"))
+                t0 = time.perf_counter()
+                cap, spl, ms = ctx.smp_tune_sketch(p, A, None if name == "ab" else B)
+                tune[name] = {"cap": cap, "splits": spl, "ms_per_launch": round(ms, 4),
+                              "tuning_s": round(time.perf_counter() - t0, 3)}
     runs = {}
     for name in legs_wanted:
         runs[name] = run_leg(ctx, api, A, B, c, seed, prec_of[name], args.steps, args.warmup, same=(name == "ab"),
@@ -700,6 +713,8 @@ def main():
         "spectral_error": errs.get(head),
     }
     out.update(legs)
+    if tune:
+        out["tune"] = tune
     if "fp32" in runs and head == "bf16":
         out["bf16_vs_fp32_solves"] = round(runs["fp32"]["ms_step"] / bf["ms_step"], 3)
     if args.copy_calibration:

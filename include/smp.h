@@ -321,6 +321,37 @@ smp_status smp_lela(smp_ctx *ctx, const smp_params *p, const float *A, int64_t l
 smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, const float *na2, double *U,
                        double *V, double *sigma);
 
+/* ---- sketch launch-shape tuning (batching and serving) -------------------------
+ * The sketch pass has two free launch parameters: the number of row splits
+ * (split-K workgroups per column tile) and, for the BF16 stored-Pi pass, the
+ * sketch-row chunk (13 or 16 m-tiles of 16 rows per workgroup). By default a
+ * cost model picks them. smp_tune_sketch times every candidate on the first
+ * rows of the given A and B that four launches of this shape cover (a launch
+ * covers one stored-Pi window, else all d rows; device pointers, layouts as
+ * smp_sketch; one warm-up and five timed passes per candidate, each costed per
+ * launch, with the reduction of the partials spread over the launches of a
+ * whole pass; Gaussian passes only,
+ * SMP_ERR_INVALID_ARG for the SRHT) and keeps the fastest in a table shared by every context of the
+ * process, keyed by (prec, k, n1, n2 or 0 when SMP_B_IS_A, rows per launch):
+ * every later sketch of that shape, in any context, uses it. It writes the
+ * choice (cap 0: the plan's own chunk) and its median cost per launch in ms. Running it
+ * while other threads sketch the same shape is allowed (they use the table as
+ * it stands); it synchronises the stream, and leaves the context's stage
+ * timing level as it was (the recorded stages are forgotten).
+ * smp_tune_save writes the table as JSON ({"format": "smp-sketch-tuning",
+ * "version": 1, "entries": [{"prec", "srht", "k", "n1", "n2", "rows", "cap",
+ * "splits", "ms"}, ...]}); smp_tune_load merges such a file into the table
+ * (SMP_ERR_INVALID_ARG for anything else, the table unchanged); the first
+ * smp_create of a process loads the file named by the environment variable
+ * SMP_TUNE_FILE, if set. smp_tune_lookup reports the stored choice for a
+ * parameter set (splits 0: none stored); smp_tune_clear empties the table. */
+smp_status smp_tune_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                           int64_t ldb, int32_t *cap, int32_t *splits, double *ms);
+smp_status smp_tune_lookup(const smp_params *p, int32_t *cap, int32_t *splits);
+smp_status smp_tune_save(const char *path);
+smp_status smp_tune_load(const char *path);
+void smp_tune_clear(void);
+
 /* ---- stage timing ------------------------------------------------------------
  * With timing enabled, smp_solve (and smp_sketch) record HIP events on the
  * context's stream around each stage; smp_stage_times writes the durations (ms)

@@ -87,6 +87,14 @@ EXPORTS = {
     "smp_sketch_push_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int64]),
+    "smp_tune_sketch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "smp_tune_lookup": (ctypes.c_int, [ctypes.POINTER(SmpParams), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "smp_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "smp_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "smp_tune_clear": (None, []),
     "smp_solve_sketched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpParams), ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),

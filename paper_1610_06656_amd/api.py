@@ -71,6 +71,34 @@ def make_params(d, n1, n2, k, r, T=10, m=None, seed=161006656, prec=_lib.SMP_PRE
     return p
 
 
+def smp_tune_lookup(p):
+    """(cap, splits) stored for this parameter set's sketch shape ((0, 0): none)."""
+    lib = _lib.load()
+    cap, spl = ctypes.c_int32(), ctypes.c_int32()
+    s = lib.smp_tune_lookup(ctypes.byref(p), ctypes.byref(cap), ctypes.byref(spl))
+    if s != _lib.SMP_OK:
+        raise SmpError(s, lib.smp_last_error(None).decode())
+    return cap.value, spl.value
+
+
+def smp_tune_save(path):
+    lib = _lib.load()
+    s = lib.smp_tune_save(str(path).encode())
+    if s != _lib.SMP_OK:
+        raise SmpError(s, lib.smp_last_error(None).decode())
+
+
+def smp_tune_load(path):
+    lib = _lib.load()
+    s = lib.smp_tune_load(str(path).encode())
+    if s != _lib.SMP_OK:
+        raise SmpError(s, lib.smp_last_error(None).decode())
+
+
+def smp_tune_clear():
+    _lib.load().smp_tune_clear()
+
+
 def smp_check_params(p):
     lib = _lib.load()
     s = lib.smp_check_params(ctypes.byref(p))
@@ -196,6 +224,18 @@ class Context:
         self._check(self.lib.smp_sketch_push_csr(self.h, st, int(which), int(row0), row_ptr.numel() - 1,
                                                  _ptr(row_ptr, torch.int64, "row_ptr"), _ptr(cols, torch.int32, "cols"),
                                                  _ptr(vals, torch.float32, "vals"), nnz))
+
+    def smp_tune_sketch(self, p, A, B):
+        """Time the sketch pass's launch shapes on A and B (B None: SMP_B_IS_A)
+        and keep the fastest for this shape; returns (cap, splits, ms)."""
+        if A.stride(1) != 1 or (B is not None and B.stride(1) != 1):
+            raise ValueError("A and B must have unit column stride")
+        cap, spl, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._check(self.lib.smp_tune_sketch(self.h, ctypes.byref(p), _ptr(A, torch.float32, "A", dense=False),
+                                             A.stride(0), _ptr(B, torch.float32, "B", dense=False),
+                                             B.stride(0) if B is not None else 0, ctypes.byref(cap),
+                                             ctypes.byref(spl), ctypes.byref(ms)))
+        return cap.value, spl.value, ms.value
 
     def smp_solve_sketched(self, p, At, Bt, na2, nb2, U, V, sigma=None):
         self._check(self.lib.smp_solve_sketched(self.h, ctypes.byref(p), _ptr(At, torch.float32, "At"),

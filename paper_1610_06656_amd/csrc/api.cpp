@@ -11,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "smp_internal.hpp"
 
@@ -92,14 +93,26 @@ SketchPlan plan_for(const smp_params *p) {
   return smp::sketch_plan(p->k, p->prec);
 }
 
+// Rows one launch covers: one stored-Pi window, else all d rows.
+int64_t launch_rows(const SketchPlan &pl, int64_t d) {
+  return pl.pi_stored ? std::min<int64_t>(d, smp::pi_window_rows(pl)) : d;
+}
+
+// The admissible split counts [smin, smax] of a Gaussian pass.
+void split_range(const SketchPlan &pl, int64_t d, int64_t &smin, int64_t &smax) {
+  const int64_t wrows = launch_rows(pl, d);
+  smin = pl.prec == SMP_PREC_FP32 ? (d + kFp32RowsPerSplit - 1) / kFp32RowsPerSplit : 1;
+  smax = std::max<int64_t>(smin, std::min<int64_t>(256, wrows / std::max(256, 2 * pl.kc)));
+}
+
 int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
   if (pl.srht) return smp::srht_splits(pl, d, n1, n2);
   const int64_t tiles = (n1 + pl.ncol_tile - 1) / pl.ncol_tile + (n2 + pl.ncol_tile - 1) / pl.ncol_tile;
   const int64_t per = (int64_t)pl.kt * tiles;
   const int64_t slots = smp::sketch_slots(pl);
-  const int64_t wrows = pl.pi_stored ? std::min<int64_t>(d, smp::pi_window_rows(pl)) : d;
-  const int64_t smin = pl.prec == SMP_PREC_FP32 ? (d + kFp32RowsPerSplit - 1) / kFp32RowsPerSplit : 1;
-  const int64_t smax = std::max<int64_t>(smin, std::min<int64_t>(256, wrows / std::max(256, 2 * pl.kc)));
+  const int64_t wrows = launch_rows(pl, d);
+  int64_t smin, smax;
+  split_range(pl, d, smin, smax);
   if (const char *e = getenv("SMP_SKETCH_SPLITS")) {   // tuning override
     const long v = strtol(e, nullptr, 10);
     if (v >= 1) return (int)std::max<int64_t>(smin, std::min<int64_t>(v, smax));
@@ -116,6 +129,33 @@ int choose_splits(const SketchPlan &pl, int64_t d, int64_t n1, int64_t n2) {
     }
   }
   return best;
+}
+
+smp::TuneKey tune_key(const smp_params *p, const SketchPlan &pl, int64_t n2) {
+  return smp::TuneKey{p->prec, (p->flags & SMP_SKETCH_SRHT) ? 1 : 0, p->k, p->n1, n2, launch_rows(pl, p->d)};
+}
+
+// While smp_tune_sketch times a candidate on this thread, it replaces the table.
+thread_local const smp::TuneChoice *t_trial = nullptr;
+
+// The launch shape of the sketch pass for a parameter set (n2 = 0 when B is
+// A): the plan, with the BF16 chunk cap that the tuning table or the trial
+// under measurement gives, and the row splits, tuned or from the cost model.
+void launch_shape(const smp_params *p, int64_t n2, SketchPlan &pl, int &S) {
+  pl = plan_for(p);
+  smp::TuneChoice c{};
+  const bool have = t_trial ? (c = *t_trial, true) : smp::tune_lookup(tune_key(p, pl, n2), c);
+  if (have && !pl.srht) {
+    if (c.cap > 0 && pl.prec == SMP_PREC_BF16 && pl.pi_stored) {
+      const SketchPlan q = smp::sketch_plan_bf16(p->k, c.cap);
+      if (q.kernel && q.kernel_clamp && q.kernel_scalar) pl = q;
+    }
+    int64_t smin, smax;
+    split_range(pl, p->d, smin, smax);
+    S = (int)std::max<int64_t>(smin, std::min<int64_t>(smax, c.splits));
+    return;
+  }
+  S = choose_splits(pl, p->d, p->n1, n2);
 }
 
 smp_status ensure(smp_ctx *ctx, Buf &b, size_t bytes) {
@@ -203,7 +243,7 @@ static void *scratch_for(int device) {
 }
 
 struct smp_ctx_bufs {
-  Buf sketch, samplews, head, omega, est, wm, mn, base, sparse;
+  Buf sketch, samplews, head, omega, est, wm, mn, base, sparse, tune;
 };
 
 namespace {
@@ -256,6 +296,10 @@ smp_status smp_create(smp_ctx **ctx, int device, void *hip_stream) {
     return fail(nullptr, SMP_ERR_DEVICE, std::string("scratch symbol lookup failed: ") + hipGetErrorString(se));
   }
   c->ws = new smp_ctx_bufs();
+  static std::once_flag tune_env;   // SMP_TUNE_FILE: a tuning file written by smp_tune_save
+  std::call_once(tune_env, [] {
+    if (const char *f = getenv("SMP_TUNE_FILE")) smp::tune_load(f);   // a missing or bad file leaves the table empty
+  });
   *ctx = c;
   return SMP_OK;
 }
@@ -266,7 +310,7 @@ void smp_destroy(smp_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
   if (b) {
-    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base, &b->sparse})
+    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base, &b->sparse, &b->tune})
       if (x->p) hipFree(x->p);
     delete b;
   }
@@ -309,13 +353,15 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes) {
   const std::string m = check(p);
   if (!m.empty()) return fail(nullptr, SMP_ERR_INVALID_ARG, m);
   if (!bytes) return fail(nullptr, SMP_ERR_INVALID_ARG, "bytes is NULL");
-  const SketchPlan pl = plan_for(p);
+  SketchPlan pl = plan_for(p);
   const int64_t nt = p->n1 + p->n2, k = p->k;
   size_t s = 0;
   // sketch partials, for B given and for B = A (smp_solve treats B == A as SMP_B_IS_A)
   for (const int64_t n2 : {p->n2, int64_t(0)}) {
     if (n2 == 0 && p->n1 != p->n2) continue;
-    const int slots = smp::sketch_slots_total(pl, choose_splits(pl, p->d, p->n1, n2));
+    int S = 0;
+    launch_shape(p, n2, pl, S);
+    const int slots = smp::sketch_slots_total(pl, S);
     s = std::max(s, al((size_t)slots * (p->n1 + n2) * pl.kpad * 4) + al((size_t)slots * (p->n1 + n2) * 8));
   }
   s += al(smp::sketch_pi_bytes(pl, p->d));                                  // stored-Pi window of the one-shot pass
@@ -344,6 +390,105 @@ smp_status smp_pi_fill(smp_ctx *ctx, const smp_params *p, int64_t l0, int64_t nr
   return SMP_OK;
 }
 
+// ---- sketch launch-shape tuning ------------------------------------------------------
+
+smp_status smp_tune_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B,
+                           int64_t ldb, int32_t *cap, int32_t *splits, double *ms) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  const std::string m = check(p);
+  if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, m);
+  if (p->flags & SMP_SKETCH_SRHT) return fail(ctx, SMP_ERR_INVALID_ARG, "tuning covers the Gaussian passes");
+  const bool same = (p->flags & SMP_B_IS_A) != 0;
+  if (!A || lda < p->n1 || (!same && (!B || ldb < p->n2)))
+    return fail(ctx, SMP_ERR_INVALID_ARG, "A/B is NULL or leading dimension too small");
+  const int64_t n2 = same ? 0 : p->n2;
+  const SketchPlan base = plan_for(p);
+  // time the pass on the rows of (up to) four launches, so that the launches
+  // after the first (which add into the partials of the ones before) weigh in
+  // as they do in a long pass; the choice applies to every launch of the shape
+  const int64_t wrows = launch_rows(base, p->d);
+  smp_params q = *p;
+  q.d = std::min<int64_t>(p->d, 4 * wrows);
+  if (q.prec == SMP_PREC_FP8 && q.d != p->d) q.d = q.d / 32 * 32;
+  const double launches = (double)((q.d + wrows - 1) / wrows);
+  smp_ctx_bufs &b = bufs(ctx);
+  const size_t ob = al(p->n1 * (size_t)p->k * 4) + al(n2 * (size_t)p->k * 4) + al(p->n1 * 4) + al(n2 * 4);
+  smp_status s = ensure(ctx, b.tune, ob);
+  if (s != SMP_OK) return s;
+  char *c = static_cast<char *>(b.tune.p);
+  float *At = take<float>(c, p->n1 * p->k);
+  float *Bt = take<float>(c, n2 * p->k);
+  float *na2 = take<float>(c, p->n1);
+  float *nb2 = take<float>(c, n2);
+  std::vector<int> caps = {0};
+  if (base.prec == SMP_PREC_BF16 && base.pi_stored) caps = {13, 16};
+  int64_t smin, smax;
+  split_range(base, q.d, smin, smax);
+  std::vector<int64_t> cands;
+  for (int64_t v : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+    if (v >= smin && v <= smax) cands.push_back(v);
+  if (cands.empty()) cands.push_back(smin);
+  // each candidate's cost: the launch (Pi window, main and tail launches) plus
+  // the reduction of its partials spread over the launches of a whole pass
+  const int saved_timing = ctx->timing;
+  s = smp_set_timing(ctx, 1);
+  if (s != SMP_OK) return s;
+  const double share = (double)q.d / (double)p->d;
+  smp::TuneChoice best{0, 0, 1e300};
+  smp_status rs = SMP_OK;
+  for (int cp : caps) {
+    for (int64_t sv : cands) {
+      const smp::TuneChoice trial{cp, (int)sv, 0.0};
+      t_trial = &trial;
+      double t[6];
+      for (int rep = 0; rep < 6 && rs == SMP_OK; ++rep) {   // one warm-up, five timed
+        rs = smp_sketch(ctx, &q, A, lda, same ? nullptr : B, ldb, At, same ? nullptr : Bt, na2, same ? nullptr : nb2);
+        float st[5] = {0, 0, 0, 0, 0};
+        if (rs == SMP_OK) rs = smp_stage_times(ctx, st, 5);
+        t[rep] = ((double)st[0] + share * (double)st[1]) / launches;
+      }
+      t_trial = nullptr;
+      if (rs != SMP_OK) break;
+      std::sort(t + 1, t + 6);
+      if (t[3] < best.ms) best = smp::TuneChoice{cp, (int)sv, t[3]};
+    }
+    if (rs != SMP_OK) break;
+  }
+  smp_set_timing(ctx, saved_timing);
+  if (rs != SMP_OK) return rs;
+  smp::tune_store(tune_key(p, base, n2), best);
+  if (cap) *cap = best.cap;
+  if (splits) *splits = best.splits;
+  if (ms) *ms = best.ms;
+  return SMP_OK;
+}
+
+smp_status smp_tune_lookup(const smp_params *p, int32_t *cap, int32_t *splits) {
+  const std::string m = check(p);
+  if (!m.empty()) return fail(nullptr, SMP_ERR_INVALID_ARG, m);
+  if (!cap || !splits) return fail(nullptr, SMP_ERR_INVALID_ARG, "cap or splits is NULL");
+  const SketchPlan pl = plan_for(p);
+  smp::TuneChoice c{};
+  if (!smp::tune_lookup(tune_key(p, pl, (p->flags & SMP_B_IS_A) ? 0 : p->n2), c)) c = smp::TuneChoice{0, 0, 0.0};
+  *cap = c.cap;
+  *splits = c.splits;
+  return SMP_OK;
+}
+
+smp_status smp_tune_save(const char *path) {
+  if (!path) return fail(nullptr, SMP_ERR_INVALID_ARG, "path is NULL");
+  const std::string e = smp::tune_save(path);
+  return e.empty() ? SMP_OK : fail(nullptr, SMP_ERR_INVALID_ARG, e);
+}
+
+smp_status smp_tune_load(const char *path) {
+  if (!path) return fail(nullptr, SMP_ERR_INVALID_ARG, "path is NULL");
+  const std::string e = smp::tune_load(path);
+  return e.empty() ? SMP_OK : fail(nullptr, SMP_ERR_INVALID_ARG, e);
+}
+
+void smp_tune_clear(void) { smp::tune_clear(); }
+
 smp_status smp_sketch_begin(smp_ctx *ctx, const smp_params *p, smp_sketch_state **st) {
   if (!ctx || !st) return fail(ctx, SMP_ERR_INVALID_ARG, "ctx or st is NULL");
   const std::string m = check(p);
@@ -352,8 +497,7 @@ smp_status smp_sketch_begin(smp_ctx *ctx, const smp_params *p, smp_sketch_state 
   if (!s) return fail(ctx, SMP_ERR_OUT_OF_MEMORY, "host allocation failed");
   s->ctx = ctx;
   s->p = *p;
-  s->plan = plan_for(p);
-  s->S = choose_splits(s->plan, p->d, p->n1, (p->flags & SMP_B_IS_A) ? 0 : p->n2);
+  launch_shape(p, (p->flags & SMP_B_IS_A) ? 0 : p->n2, s->plan, s->S);
   const int64_t n2 = (p->flags & SMP_B_IS_A) ? 0 : p->n2;
   const int64_t nt = p->n1 + n2;
   const int slots = smp::sketch_slots_total(s->plan, s->S);
@@ -503,9 +647,10 @@ smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t
   if (!same && (!B || ldb < p->n2)) return fail(ctx, SMP_ERR_INVALID_ARG, "B is NULL or ldb < n2");
   if (!At || !na2 || (!same && (!Bt || !nb2))) return fail(ctx, SMP_ERR_INVALID_ARG, "output pointer is NULL");
   // the one-shot pass keeps its partials in the context's workspace
-  const SketchPlan pl = plan_for(p);
-  const int64_t n2 = same ? 0 : p->n2;
-  const int S = choose_splits(pl, p->d, p->n1, n2);   // B = A: only A's column tiles run
+  const int64_t n2 = same ? 0 : p->n2;   // B = A: only A's column tiles run
+  SketchPlan pl;
+  int S = 0;
+  launch_shape(p, n2, pl, S);
   const int64_t nt = p->n1 + n2;
   const int slots = smp::sketch_slots_total(pl, S);
   const size_t pb = al((size_t)slots * nt * pl.kpad * 4), nb = al((size_t)slots * nt * 8);

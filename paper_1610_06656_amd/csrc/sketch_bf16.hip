@@ -671,12 +671,12 @@ static SketchPlan sketch_plan_bf16_regen(int k) {
 // workgroup, `depth` K steps of loads in flight.
 // SMP_SKETCH_BF16_STORED="nv,waves,depth,cap" picks the shape, "0" selects
 // the regenerating pass above.
-SketchPlan sketch_plan_bf16(int k) {
+SketchPlan sketch_plan_bf16(int k, int cap_in) {
   // up to 16 m-tiles per chunk: at k = 1,024 every data tile is read by 4
   // chunks instead of 5 with 13 (22.8 -> 19.8 ms at d = 10^6, n = 8,192);
   // one wave per SIMD with the accumulators in AGPRs (nv 4, 4 waves) was
   // slower (21.7 ms): it spills and leaves less latency hidden
-  int nv = 2, waves = 8, depth = 2, cap = 16;
+  int nv = 2, waves = 8, depth = 2, cap = cap_in >= 1 && cap_in <= 16 ? cap_in : 16;
   if (const char *e = getenv("SMP_SKETCH_BF16_STORED")) {
     int env[4] = {0, 0, 0, 0};
     const int got = sscanf(e, "%d,%d,%d,%d", &env[0], &env[1], &env[2], &env[3]);

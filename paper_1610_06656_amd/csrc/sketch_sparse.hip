@@ -405,7 +405,6 @@ hipError_t sparse_prepare(const SketchPlan &pl, const SparseIn &in, int64_t d, i
                        d, n, dbits, w.srt.keys0, w.srt.vals0, w.st);
   if ((e = radix_sort(w.srt, &w.st->nnz, kbits, st)) != hipSuccess) return e;
   const uint64_t *keys = radix_result(w.srt, kbits);
-  const uint32_t *pay = radix_payload(w.srt, kbits);
   hipLaunchKernelGGL(sp_col_ptr_kernel, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, keys, w.st, n, dbits,
                      w.col_ptr);
   hipLaunchKernelGGL(sp_repeats_kernel, dim3(blocks_for(in.nnz, 256)), dim3(256), 0, st, keys, w.st);

@@ -67,7 +67,7 @@ inline int sketch_slots_total(const SketchPlan &pl, int S) { return pl.prec == S
 
 // Tile plan for sketch size k and operand precision prec.
 SketchPlan sketch_plan(int k, int prec);
-SketchPlan sketch_plan_bf16(int k);
+SketchPlan sketch_plan_bf16(int k, int cap = 0);   // cap: m-tiles per chunk of the stored-Pi pass (0: default)
 SketchPlan sketch_plan_fp8(int k);
 
 // Stored-Pi passes draw Pi one window at a time into a buffer of at most
@@ -142,6 +142,24 @@ hipError_t scan_exclusive(const SortWs &w, const int64_t *in, int64_t n, int64_t
 hipError_t radix_sort(const SortWs &w, const int64_t *n_dev, int bits, hipStream_t st);
 inline const uint64_t *radix_result(const SortWs &w, int bits) { return ((bits + 7) / 8) % 2 ? w.keys1 : w.keys0; }
 inline const uint32_t *radix_payload(const SortWs &w, int bits) { return ((bits + 7) / 8) % 2 ? w.vals1 : w.vals0; }
+
+// ---- launch-shape table of the sketch pass (tune.cpp) -------------------------
+// rows: the rows one launch covers (one stored-Pi window, else d); n2 = 0
+// when B is A; cap 0 keeps the plan's own chunk cap.
+struct TuneKey {
+  int prec, srht, k;
+  int64_t n1, n2, rows;
+};
+struct TuneChoice {
+  int cap, splits;
+  double ms;
+};
+bool tune_lookup(const TuneKey &k, TuneChoice &out);
+void tune_store(const TuneKey &k, const TuneChoice &c);
+void tune_clear();
+size_t tune_count();
+std::string tune_save(const char *path);   // "" on success, else the problem
+std::string tune_load(const char *path);
 
 // ---- entry-wise sketch (sketch_sparse.hip) ----------------------------------
 // One push of triples (l, i, v) of one matrix (COO: rows; CSR: row_ptr over
