@@ -321,6 +321,21 @@ smp_status smp_lela(smp_ctx *ctx, const smp_params *p, const float *A, int64_t l
 smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, const float *na2, double *U,
                        double *V, double *sigma);
 
+/* WAltMin for a group of jobs resident at once (batching and serving): job j
+ * is exactly smp_waltmin(ctx, &p[j], &om[j], na2[j], U[j], V[j], sigma[j])
+ * (sigma may be NULL, or sigma[j] NULL, as there), bit for bit. The jobs'
+ * launch sequences are recorded on the host and grouped by sequence (the same
+ * r, T, init_iters, omega_mode and block-width class give the same kernels in
+ * the same order); each group then runs as one launch per step over all its
+ * jobs, each kernel finding its job's arguments in a device table (blockIdx.y
+ * = job), and with graph != 0 as one HIP graph per group (captured, launched
+ * once and released; the table is copied before the capture, so the graph
+ * holds kernel nodes only). The context keeps one workspace for all jobs
+ * (their WAltMin workspaces plus the tables). Synchronises the stream. */
+smp_status smp_waltmin_group(smp_ctx *ctx, int njobs, const smp_params *p, const smp_omega *om,
+                             const float *const *na2, double *const *U, double *const *V, double *const *sigma,
+                             int graph);
+
 /* ---- sketch launch-shape tuning (batching and serving) -------------------------
  * The sketch pass has two free launch parameters: the number of row splits
  * (split-K workgroups per column tile) and, for the BF16 stored-Pi pass, the

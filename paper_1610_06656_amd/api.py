@@ -269,6 +269,21 @@ class Context:
                                          _ptr(U, torch.float64, "U"), _ptr(V, torch.float64, "V"),
                                          _ptr(sigma, torch.float64, "sigma")))
 
+    def smp_waltmin_group(self, params, omegas, na2s, Us, Vs, sigmas=None, graph=True):
+        """smp_waltmin for every job of the lists at once (grouped launches,
+        one HIP graph per group of equal launch sequences with graph=True)."""
+        n = len(params)
+        if not (len(omegas) == len(na2s) == len(Us) == len(Vs) == n) or (sigmas is not None and len(sigmas) != n):
+            raise ValueError("job lists differ in length")
+        P = (SmpParams * max(1, n))(*params)
+        O = (SmpOmega * max(1, n))(*[o.struct() for o in omegas])
+        ptrs = lambda ts, dt, nm: (ctypes.c_void_p * max(1, n))(*[_ptr(t, dt, nm) for t in ts])
+        na = ptrs(na2s, torch.float32, "na2")
+        U = ptrs(Us, torch.float64, "U")
+        V = ptrs(Vs, torch.float64, "V")
+        S = ptrs(sigmas, torch.float64, "sigma") if sigmas is not None else None
+        self._check(self.lib.smp_waltmin_group(self.h, n, P, O, na, U, V, S, int(bool(graph))))
+
     def smp_set_timing(self, enable=True):
         """True or 1: every stage; 2: the sketch stage only; False or 0: off."""
         self._check(self.lib.smp_set_timing(self.h, int(enable)))

@@ -243,7 +243,7 @@ static void *scratch_for(int device) {
 }
 
 struct smp_ctx_bufs {
-  Buf sketch, samplews, head, omega, est, wm, mn, base, sparse, tune;
+  Buf sketch, samplews, head, omega, est, wm, mn, base, sparse, tune, group;
 };
 
 namespace {
@@ -310,7 +310,7 @@ void smp_destroy(smp_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   auto *b = static_cast<smp_ctx_bufs *>(ctx->ws);
   if (b) {
-    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base, &b->sparse, &b->tune})
+    for (Buf *x : {&b->sketch, &b->samplews, &b->head, &b->omega, &b->est, &b->wm, &b->mn, &b->base, &b->sparse, &b->tune, &b->group})
       if (x->p) hipFree(x->p);
     delete b;
   }
@@ -837,6 +837,41 @@ smp_status smp_waltmin(smp_ctx *ctx, const smp_params *p, const smp_omega *om, c
   if (p->omega_mode == SMP_OMEGA_SPLIT && om->nnz > 0 && (!om->sub_csr || !om->sub_csc))
     return fail(ctx, SMP_ERR_INVALID_ARG, "SPLIT mode needs sub_csr and sub_csc");
   return waltmin_call(ctx, p, om, na2, U, V, sigma, nullptr);
+}
+
+smp_status smp_waltmin_group(smp_ctx *ctx, int njobs, const smp_params *p, const smp_omega *om,
+                             const float *const *na2, double *const *U, double *const *V, double *const *sigma,
+                             int graph) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  if (njobs < 0) return fail(ctx, SMP_ERR_INVALID_ARG, "njobs < 0");
+  if (njobs == 0) return SMP_OK;
+  if (!p || !om || !na2 || !U || !V) return fail(ctx, SMP_ERR_INVALID_ARG, "an array argument is NULL");
+  size_t total = 0;
+  std::vector<size_t> wsz(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    const std::string m = check(&p[j]);
+    if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, "job " + std::to_string(j) + ": " + m);
+    if (!na2[j] || !U[j] || !V[j]) return fail(ctx, SMP_ERR_INVALID_ARG, "job " + std::to_string(j) + ": NULL pointer");
+    if (om[j].n1 != p[j].n1 || om[j].n2 != p[j].n2)
+      return fail(ctx, SMP_ERR_INVALID_ARG, "job " + std::to_string(j) + ": om grid differs from params");
+    if (p[j].omega_mode == SMP_OMEGA_SPLIT && om[j].nnz > 0 && (!om[j].sub_csr || !om[j].sub_csc))
+      return fail(ctx, SMP_ERR_INVALID_ARG, "job " + std::to_string(j) + ": SPLIT mode needs sub_csr and sub_csc");
+    wsz[j] = al(smp::waltmin_ws_bytes(p[j].n1, p[j].n2, p[j].r, om[j].nnz));
+    total += wsz[j];
+  }
+  const size_t tb = al(smp::waltmin_group_table_bytes(njobs, p, om));
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.group, total + tb);
+  if (s != SMP_OK) return s;
+  std::vector<void *> ws(njobs);
+  char *c = static_cast<char *>(b.group.p);
+  for (int j = 0; j < njobs; ++j) {
+    ws[j] = c;
+    c += wsz[j];
+  }
+  SMP_HIP(ctx, smp::waltmin_group_run(njobs, p, om, na2, U, V, sigma, ws.data(), nullptr, c, graph, ctx->stream));
+  SMP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return SMP_OK;
 }
 
 static smp_status solve_after_sketch(smp_ctx *ctx, const smp_params &q, const float *At, const float *Bt,

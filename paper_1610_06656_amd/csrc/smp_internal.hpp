@@ -217,6 +217,13 @@ hipError_t estimate_run(const float *At, const float *Bt, const float *na2, cons
 
 // ---- WAltMin -------------------------------------------------------------------
 size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t nnz);
+// A group of jobs (see waltmin.hip): table_ws holds waltmin_group_table_bytes;
+// fa null (or fa[j] null): F_A summed from na2 per job; graph: one HIP graph per
+// bucket of jobs with the same launch sequence. Synchronises the stream.
+size_t waltmin_group_table_bytes(int njobs, const smp_params *prm, const smp_omega *om);
+hipError_t waltmin_group_run(int njobs, const smp_params *prm, const smp_omega *om, const float *const *na2,
+                             double *const *Uout, double *const *Vout, double *const *sigma, void *const *wsbase,
+                             const double *const *fa, void *table_ws, int graph, hipStream_t st);
 hipError_t waltmin_run(const smp_params &p, const smp_omega &om, const float *na2, double *U, double *V,
                        double *sigma, void *ws, hipStream_t st,
                        const double *fa_in);   // F_A on the device, or null to sum it from na2

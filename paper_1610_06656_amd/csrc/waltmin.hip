@@ -58,6 +58,59 @@ __device__ __forceinline__ double readlane_f64(double v, int src) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// ---------------------------------------------------------------- launches
+// Every kernel below is a device body taking one argument struct, launched
+// either for one job (k_one: the struct by value) or for a group of jobs
+// (k_group: blockIdx.y picks the job's struct in a device table). The host
+// code issues its launches through an Exec: it launches them on a stream, or
+// records them (kernel, grid, the job's struct) so that the same sequence,
+// recorded for every job of a group, runs as one launch per step with
+// grid.x the largest of the jobs' grids (blocks past a job's own grid find
+// nothing to do) and grid.y the number of jobs.
+template <class A, void (*F)(const A &), int LB, int MINB>
+__global__ __launch_bounds__(LB, MINB) void k_one(A a) {
+  F(a);
+}
+template <class A, void (*F)(const A &), int LB, int MINB>
+__global__ __launch_bounds__(LB, MINB) void k_group(const A *__restrict__ table) {
+  F(table[blockIdx.y]);
+}
+
+struct Op {
+  const void *id;   // the group kernel: recordings of different jobs must agree step by step
+  dim3 grid, block;
+  std::vector<char> arg;
+  void (*launch)(const void *table, dim3 grid, dim3 block, hipStream_t st);
+};
+
+class Exec {
+ public:
+  explicit Exec(hipStream_t st) : st_(st) {}
+  explicit Exec(std::vector<Op> *rec) : rec_(rec) {}
+  hipStream_t stream() const { return st_; }
+  bool recording() const { return rec_ != nullptr; }
+  template <class A, void (*F)(const A &), int LB, int MINB = 1>
+  void run(dim3 grid, dim3 block, const A &a) {
+    if (!rec_) {
+      hipLaunchKernelGGL((k_one<A, F, LB, MINB>), grid, block, 0, st_, a);
+      return;
+    }
+    Op o;
+    o.id = reinterpret_cast<const void *>(&k_group<A, F, LB, MINB>);
+    o.grid = grid;
+    o.block = block;
+    o.arg.assign(reinterpret_cast<const char *>(&a), reinterpret_cast<const char *>(&a) + sizeof(A));
+    o.launch = [](const void *table, dim3 g, dim3 b, hipStream_t s) {
+      hipLaunchKernelGGL((k_group<A, F, LB, MINB>), g, b, 0, s, static_cast<const A *>(table));
+    };
+    rec_->push_back(std::move(o));
+  }
+
+ private:
+  hipStream_t st_ = nullptr;
+  std::vector<Op> *rec_ = nullptr;
+};
+
 // ---------------------------------------------------------------- Gram
 // part[b][a*p + c] = sum over the rows of block b of X[i][a] X[i][c], on the
 // FP64 matrix cores: wave w of the block takes the row quads w, w + 4, ...
@@ -67,9 +120,19 @@ __device__ __forceinline__ double readlane_f64(double v, int src) {
 // block and columns past p load a clamped in-range element and are masked to
 // zero afterwards (unconditional loads keep several quads in flight). The four
 // waves' tiles are summed in LDS in a fixed order (wave 3, then 2, 1, 0).
+struct GramArgs {
+  const double *X;
+  int64_t n;
+  int p;
+  int64_t rows_per_block;
+  double *part;
+};
 template <int RT>
-__global__ __launch_bounds__(256) void gram_partial_kernel(const double *__restrict__ X, int64_t n, int p,
-                                                           int64_t rows_per_block, double *__restrict__ part) {
+__device__ __forceinline__ void gram_partial_body(const GramArgs &a_) {
+  const double *__restrict__ X = a_.X;
+  const int64_t n = a_.n, rows_per_block = a_.rows_per_block;
+  const int p = a_.p;
+  double *__restrict__ part = a_.part;
   constexpr int D = 16 * RT;
   constexpr int B = 4;
   __shared__ double S[D * D];
@@ -152,9 +215,18 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
 // in registers: lane i holds row i of G (then of L), pivots and entries are
 // broadcast with v_readlane, the same operations in the same order; lane t
 // then computes column t of L^-1 and writes row t of M.
+struct CholArgs {
+  const double *part;
+  int nblk, p;
+  double shift_rel;
+  double *M;
+};
 template <int D>
-__global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict__ part, int nblk, int p,
-                                                       double shift_rel, double *__restrict__ M) {
+__device__ __forceinline__ void chol_inv_body(const CholArgs &a_) {
+  const double *__restrict__ part = a_.part;
+  const int nblk = a_.nblk, p = a_.p;
+  const double shift_rel = a_.shift_rel;
+  double *__restrict__ M = a_.M;
   __shared__ double L[kMaxP * kMaxP];
   __shared__ double Y[kMaxP * kMaxP];
   __shared__ double dinv[kMaxP];
@@ -256,10 +328,27 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double *__restrict_
 // na2 is given, rows of Xo1 whose norm exceeds 8 sqrt(pout) sqrt(na2_i / FA)
 // are set to zero (the trim of Alg. 2 step 6; the squared norm is summed in
 // column order).
-__global__ void apply2_kernel(const double *__restrict__ X1, int64_t n1, const double *__restrict__ M1,
-                              double *__restrict__ Xo1, const float *__restrict__ na2, const double *__restrict__ FA,
-                              const double *__restrict__ X2, int64_t n2, const double *__restrict__ M2,
-                              double *__restrict__ Xo2, int pin, int pout, int64_t nb1) {
+struct Apply2Args {
+  const double *X1;
+  int64_t n1;
+  const double *M1;
+  double *Xo1;
+  const float *na2;
+  const double *FA;
+  const double *X2;
+  int64_t n2;
+  const double *M2;
+  double *Xo2;
+  int pin, pout;
+  int64_t nb1;
+};
+__device__ __forceinline__ void apply2_body(const Apply2Args &a_) {
+  const double *__restrict__ X1 = a_.X1, *__restrict__ M1 = a_.M1, *__restrict__ FA = a_.FA;
+  const double *__restrict__ X2 = a_.X2, *__restrict__ M2 = a_.M2;
+  double *__restrict__ Xo1 = a_.Xo1, *__restrict__ Xo2 = a_.Xo2;
+  const float *__restrict__ na2 = a_.na2;
+  const int64_t n1 = a_.n1, n2 = a_.n2, nb1 = a_.nb1;
+  const int pin = a_.pin, pout = a_.pout;
   const int lane = threadIdx.x & 63;
   const bool first = blockIdx.x < nb1;
   const int64_t i = (first ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - nb1) * 4 + (threadIdx.x >> 6);
@@ -285,8 +374,20 @@ __global__ void apply2_kernel(const double *__restrict__ X1, int64_t n1, const d
 // Xout (n x pout) = X (n x pin) * M (pin x pout), row-major. One wave per row,
 // lane a computes output column a; every lane reads the whole input row before
 // any lane writes, so Xout may alias X when pin == pout.
-__global__ void apply_kernel(const double *X, int64_t n, int pin, const double *__restrict__ M, int pout,
-                             double *Xout) {
+struct ApplyArgs {
+  const double *X;
+  int64_t n;
+  int pin;
+  const double *M;
+  int pout;
+  double *Xout;
+};
+__device__ __forceinline__ void apply_body(const ApplyArgs &a_) {
+  const double *X = a_.X;   // may alias Xout
+  const int64_t n = a_.n;
+  const int pin = a_.pin, pout = a_.pout;
+  const double *__restrict__ M = a_.M;
+  double *Xout = a_.Xout;
   const int lane = threadIdx.x & 63;
   const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= n) return;
@@ -335,10 +436,16 @@ __device__ __forceinline__ void jacobi_pair(int rd, int k, int m, int &P, int &Q
   }
 }
 
+struct JacobiArgs {
+  const double *part;
+  int nblk, p, r;
+  double *Mu, *Mv, *sigma;
+};
 template <int NT>
-__global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict__ part, int nblk, int p, int r,
-                                                        double *__restrict__ Mu, double *__restrict__ Mv,
-                                                        double *__restrict__ sigma) {
+__device__ __forceinline__ void jacobi_eig_body(const JacobiArgs &a_) {
+  const double *__restrict__ part = a_.part;
+  const int nblk = a_.nblk, p = a_.p, r = a_.r;
+  double *__restrict__ Mu = a_.Mu, *__restrict__ Mv = a_.Mv, *__restrict__ sigma = a_.sigma;
   __shared__ double A[kMaxP * kMaxP];
   __shared__ double V[kMaxP * kMaxP];
   __shared__ double cs[kMaxP / 2][2];
@@ -462,13 +569,14 @@ __global__ __launch_bounds__(NT) void jacobi_eig_kernel(const double *__restrict
 
 // The rounds are latency-bound chains (rotation, then the column and row
 // updates); more threads shorten the update phases of the larger problems.
-void jacobi_eig(const double *part, int nblk, int p, int r, double *Mu, double *Mv, double *sigma, hipStream_t st) {
+void jacobi_eig(Exec &ex, const double *part, int nblk, int p, int r, double *Mu, double *Mv, double *sigma) {
+  const JacobiArgs a{part, nblk, p, r, Mu, Mv, sigma};
   if (p <= 10)
-    hipLaunchKernelGGL(jacobi_eig_kernel<64>, dim3(1), dim3(64), 0, st, part, nblk, p, r, Mu, Mv, sigma);
+    ex.run<JacobiArgs, jacobi_eig_body<64>, 64>(dim3(1), dim3(64), a);
   else if (p <= 32)
-    hipLaunchKernelGGL(jacobi_eig_kernel<256>, dim3(1), dim3(256), 0, st, part, nblk, p, r, Mu, Mv, sigma);
+    ex.run<JacobiArgs, jacobi_eig_body<256>, 256>(dim3(1), dim3(256), a);
   else
-    hipLaunchKernelGGL(jacobi_eig_kernel<1024>, dim3(1), dim3(1024), 0, st, part, nblk, p, r, Mu, Mv, sigma);
+    ex.run<JacobiArgs, jacobi_eig_body<1024>, 1024>(dim3(1), dim3(1024), a);
 }
 
 // ---------------------------------------------------------------- sparse products
@@ -481,12 +589,28 @@ void jacobi_eig(const double *part, int nblk, int p, int r, double *Mu, double *
 // next chunk's metadata is requested after the first batch of rows, so that
 // one memory round trip serves both. Partial sums are combined with shuffles
 // within a wave and through LDS across waves.
+struct SpmmArgs {
+  const int64_t *ptr;
+  const int32_t *idx;
+  const double *w, *mt;
+  const uint8_t *sub;
+  int sel;
+  const double *Y;
+  int p;
+  int64_t n_out;
+  const double *Mpost;
+  double *Xout;
+};
 template <int G>
-__global__ __launch_bounds__(256) void spmm_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                   const double *__restrict__ w, const double *__restrict__ mt,
-                                                   const uint8_t *__restrict__ sub, int sel,
-                                                   const double *__restrict__ Y, int p, int64_t n_out,
-                                                   const double *__restrict__ Mpost, double *__restrict__ Xout) {
+__device__ __forceinline__ void spmm_body(const SpmmArgs &a_) {
+  const int64_t *__restrict__ ptr = a_.ptr;
+  const int32_t *__restrict__ idx = a_.idx;
+  const double *__restrict__ w = a_.w, *__restrict__ mt = a_.mt, *__restrict__ Y = a_.Y;
+  const double *__restrict__ Mpost = a_.Mpost;
+  const uint8_t *__restrict__ sub = a_.sub;
+  const int sel = a_.sel, p = a_.p;
+  const int64_t n_out = a_.n_out;
+  double *__restrict__ Xout = a_.Xout;
   constexpr int NG = 64 / G;
   __shared__ double red[4 * 64];
   __shared__ double xs[64];
@@ -558,7 +682,17 @@ __global__ __launch_bounds__(256) void spmm_kernel(const int64_t *__restrict__ p
   }
 }
 
-__global__ void gaussian_block_kernel(int64_t n, int p, uint64_t seed, double *__restrict__ Y) {
+struct GaussArgs {
+  int64_t n;
+  int p;
+  uint64_t seed;
+  double *Y;
+};
+__device__ __forceinline__ void gaussian_block_body(const GaussArgs &a_) {
+  const int64_t n = a_.n;
+  const int p = a_.p;
+  const uint64_t seed = a_.seed;
+  double *__restrict__ Y = a_.Y;
   const int nb4 = (p + 3) / 4;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nb4; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / nb4;
@@ -571,15 +705,34 @@ __global__ void gaussian_block_kernel(int64_t n, int p, uint64_t seed, double *_
 }
 
 // ---------------------------------------------------------------- scale, sign
-__global__ void scale_cols_kernel(double *__restrict__ U, int64_t n, int r, const double *__restrict__ s) {
+struct ScaleArgs {
+  double *U;
+  int64_t n;
+  int r;
+  const double *s;
+};
+__device__ __forceinline__ void scale_cols_body(const ScaleArgs &a_) {
+  double *__restrict__ U = a_.U;
+  const int64_t n = a_.n;
+  const int r = a_.r;
+  const double *__restrict__ s = a_.s;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * r; e += (int64_t)gridDim.x * blockDim.x)
     U[e] *= s[e % r];
 }
 
 // One workgroup per component c: sign of the largest-magnitude entry of V[:, c]
 // (first index on ties); flips U[:, c] and V[:, c] when it is negative.
-__global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, int64_t n1, double *__restrict__ V,
-                                                       int64_t n2, int r) {
+struct SignArgs {
+  double *U;
+  int64_t n1;
+  double *V;
+  int64_t n2;
+  int r;
+};
+__device__ __forceinline__ void sign_fix_body(const SignArgs &a_) {
+  double *__restrict__ U = a_.U, *__restrict__ V = a_.V;
+  const int64_t n1 = a_.n1, n2 = a_.n2;
+  const int r = a_.r;
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
   const int c = blockIdx.x, t = threadIdx.x;
@@ -617,12 +770,26 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double *__restrict__ U, i
 // after the first batch of rows, so that the two loads overlap. The four waves'
 // Gram tiles are summed in LDS and the r x r system is solved there.
 // R > 0: the instantiation for r = R (RT = 1 only); R = 0: any r of the tile width.
+struct LsArgs {
+  const int64_t *ptr;
+  const int32_t *idx;
+  const double *w, *mt;
+  const uint8_t *sub;
+  int sel;
+  const double *Q;
+  int r;
+  int64_t n_out;
+  double *Xout;
+};
 template <int RT, int R>
-__global__ __launch_bounds__(256, RT == 1 ? 5 : 1) void ls_solve_kernel(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                       const double *__restrict__ w, const double *__restrict__ mt,
-                                                       const uint8_t *__restrict__ sub, int sel,
-                                                       const double *__restrict__ Q, int r, int64_t n_out,
-                                                       double *__restrict__ Xout) {
+__device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
+  const int64_t *__restrict__ ptr = a_.ptr;
+  const int32_t *__restrict__ idx = a_.idx;
+  const double *__restrict__ w = a_.w, *__restrict__ mt = a_.mt, *__restrict__ Q = a_.Q;
+  const uint8_t *__restrict__ sub = a_.sub;
+  const int sel = a_.sel, r = a_.r;
+  const int64_t n_out = a_.n_out;
+  double *__restrict__ Xout = a_.Xout;
   static_assert(RT != 1 || R > 0, "the one-tile kernel is instantiated per r");
   constexpr int D = RT * 16;
   constexpr int BATCH = RT == 1 ? 16 : (RT == 2 ? 8 : 4);
@@ -963,111 +1130,116 @@ size_t carve_bytes(int64_t n1, int64_t n2, int p, int r) {
   return s;
 }
 
-int gram(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
+int gram(Exec &ex, const Ws &w, const double *X, int64_t n, int p) {
   const int nblk = (int)std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + 127) / 128));
   const int64_t rpb = (n + nblk - 1) / nblk;
   const dim3 grid((unsigned)nblk), blk(256);
+  const GramArgs a{X, n, p, rpb, w.part};
   if (p <= 16)
-    hipLaunchKernelGGL(gram_partial_kernel<1>, grid, blk, 0, st, X, n, p, rpb, w.part);
+    ex.run<GramArgs, gram_partial_body<1>, 256>(grid, blk, a);
   else if (p <= 32)
-    hipLaunchKernelGGL(gram_partial_kernel<2>, grid, blk, 0, st, X, n, p, rpb, w.part);
+    ex.run<GramArgs, gram_partial_body<2>, 256>(grid, blk, a);
   else if (p <= 48)
-    hipLaunchKernelGGL(gram_partial_kernel<3>, grid, blk, 0, st, X, n, p, rpb, w.part);
+    ex.run<GramArgs, gram_partial_body<3>, 256>(grid, blk, a);
   else
-    hipLaunchKernelGGL(gram_partial_kernel<4>, grid, blk, 0, st, X, n, p, rpb, w.part);
+    ex.run<GramArgs, gram_partial_body<4>, 256>(grid, blk, a);
   return nblk;
 }
 
-
-void apply2(const double *X1, int64_t n1, const double *M1, double *Xo1, const float *na2, const double *FA,
-            const double *X2, int64_t n2, const double *M2, double *Xo2, int pin, int pout, hipStream_t st) {
+void apply2(Exec &ex, const double *X1, int64_t n1, const double *M1, double *Xo1, const float *na2, const double *FA,
+            const double *X2, int64_t n2, const double *M2, double *Xo2, int pin, int pout) {
   const int64_t nb1 = cdiv(n1, 4), nb2 = cdiv(n2, 4);
-  hipLaunchKernelGGL(apply2_kernel, dim3((unsigned)(nb1 + nb2)), dim3(256), 0, st, X1, n1, M1, Xo1, na2, FA, X2, n2, M2,
-                     Xo2, pin, pout, nb1);
+  ex.run<Apply2Args, apply2_body, 256>(dim3((unsigned)(nb1 + nb2)), dim3(256),
+                                       Apply2Args{X1, n1, M1, Xo1, na2, FA, X2, n2, M2, Xo2, pin, pout, nb1});
 }
 
-void apply(const double *X, int64_t n, int pin, const double *M, int pout, double *Xout, hipStream_t st) {
-  hipLaunchKernelGGL(apply_kernel, dim3(cdiv(n, 4)), dim3(256), 0, st, X, n, pin, M, pout, Xout);
+void apply(Exec &ex, const double *X, int64_t n, int pin, const double *M, int pout, double *Xout) {
+  ex.run<ApplyArgs, apply_body, 256>(dim3(cdiv(n, 4)), dim3(256), ApplyArgs{X, n, pin, M, pout, Xout});
+}
+
+void chol_inv(Exec &ex, const Ws &w, int nblk, int p, double shift_rel) {
+  const CholArgs a{w.part, nblk, p, shift_rel, w.M};
+  if (p <= 16)
+    ex.run<CholArgs, chol_inv_body<16>, 256>(dim3(1), dim3(256), a);
+  else if (p <= 32)
+    ex.run<CholArgs, chol_inv_body<32>, 256>(dim3(1), dim3(256), a);
+  else
+    ex.run<CholArgs, chol_inv_body<0>, 256>(dim3(1), dim3(256), a);
 }
 
 // X (n x p) <- X L^-T for X^T X (+ a tiny shift) = L L^T: one CholeskyQR pass,
 // span preserved; twice gives orthonormal columns to working precision.
-void cholqr_pass(const Ws &w, const double *X, int64_t n, int p, double shift_rel, double *Xout, hipStream_t st) {
-  const int nblk = gram(w, X, n, p, st);
-  if (p <= 16)
-    hipLaunchKernelGGL(chol_inv_kernel<16>, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
-  else if (p <= 32)
-    hipLaunchKernelGGL(chol_inv_kernel<32>, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
-  else
-    hipLaunchKernelGGL(chol_inv_kernel<0>, dim3(1), dim3(256), 0, st, w.part, nblk, p, shift_rel, w.M);
-  apply(X, n, p, w.M, p, Xout, st);
+void cholqr_pass(Exec &ex, const Ws &w, const double *X, int64_t n, int p, double shift_rel, double *Xout) {
+  chol_inv(ex, w, gram(ex, w, X, n, p), p, shift_rel);
+  apply(ex, X, n, p, w.M, p, Xout);
 }
 
 // X (n x p) <- orthonormal basis of its span (CholeskyQR2, in place).
-void orth(const Ws &w, double *X, int64_t n, int p, hipStream_t st) {
-  cholqr_pass(w, X, n, p, 1e-14, X, st);
-  cholqr_pass(w, X, n, p, 0.0, X, st);
+void orth(Exec &ex, const Ws &w, double *X, int64_t n, int p) {
+  cholqr_pass(ex, w, X, n, p, 1e-14, X);
+  cholqr_pass(ex, w, X, n, p, 0.0, X);
 }
 
 // The map of one shifted CholeskyQR pass (X^T X + shift = L L^T, w.M = L^-T),
 // without applying it: the next sparse product multiplies its output by w.M
 // (span kept; X w.M has orthonormal columns up to O(eps cond(X)^2), enough to
 // condition the next product).
-void orth1_map(const Ws &w, const double *X, int64_t n, int p, hipStream_t st) {
-  const int nblk = gram(w, X, n, p, st);
-  if (p <= 16)
-    hipLaunchKernelGGL(chol_inv_kernel<16>, dim3(1), dim3(256), 0, st, w.part, nblk, p, 1e-14, w.M);
-  else if (p <= 32)
-    hipLaunchKernelGGL(chol_inv_kernel<32>, dim3(1), dim3(256), 0, st, w.part, nblk, p, 1e-14, w.M);
-  else
-    hipLaunchKernelGGL(chol_inv_kernel<0>, dim3(1), dim3(256), 0, st, w.part, nblk, p, 1e-14, w.M);
+void orth1_map(Exec &ex, const Ws &w, const double *X, int64_t n, int p) {
+  chol_inv(ex, w, gram(ex, w, X, n, p), p, 1e-14);
 }
 
 // Xout = R Y (CSR side) or R^T Y (CSC side), times Mpost (p x p) when given.
-void spmm(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
-          const double *Y, int p, int64_t n_out, const double *Mpost, double *Xout, hipStream_t st) {
+void spmm(Exec &ex, const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub,
+          int sel, const double *Y, int p, int64_t n_out, const double *Mpost, double *Xout) {
   const dim3 grid((unsigned)std::max<int64_t>(1, n_out)), blk(256);
+  const SpmmArgs a{ptr, idx, wt, mt, sub, sel, Y, p, n_out, Mpost, Xout};
   if (p <= 16)
-    hipLaunchKernelGGL(spmm_kernel<16>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Mpost, Xout);
+    ex.run<SpmmArgs, spmm_body<16>, 256>(grid, blk, a);
   else if (p <= 32)
-    hipLaunchKernelGGL(spmm_kernel<32>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Mpost, Xout);
+    ex.run<SpmmArgs, spmm_body<32>, 256>(grid, blk, a);
   else
-    hipLaunchKernelGGL(spmm_kernel<64>, grid, blk, 0, st, ptr, idx, wt, mt, sub, sel, Y, p, n_out, Mpost, Xout);
+    ex.run<SpmmArgs, spmm_body<64>, 256>(grid, blk, a);
 }
 
 template <int R>
-void ls_solve_r(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub,
-                int sel, const double *Q, int64_t n_out, double *Xout, hipStream_t st) {
-  hipLaunchKernelGGL((ls_solve_kernel<1, R>), dim3((unsigned)std::max<int64_t>(1, n_out)), dim3(256), 0, st, ptr, idx,
-                     wt, mt, sub, sel, Q, R, n_out, Xout);
+void ls_solve_r(Exec &ex, const LsArgs &a) {
+  ex.run<LsArgs, ls_solve_body<1, R>, 256, 5>(dim3((unsigned)std::max<int64_t>(1, a.n_out)), dim3(256), a);
 }
 
-typedef void (*LsLaunch)(const int64_t *, const int32_t *, const double *, const double *, const uint8_t *, int,
-                         const double *, int64_t, double *, hipStream_t);
+typedef void (*LsLaunch)(Exec &, const LsArgs &);
 const LsLaunch kLsByR[16] = {nullptr,       ls_solve_r<1>,  ls_solve_r<2>,  ls_solve_r<3>,  ls_solve_r<4>,
                              ls_solve_r<5>,  ls_solve_r<6>,  ls_solve_r<7>,  ls_solve_r<8>,  ls_solve_r<9>,
                              ls_solve_r<10>, ls_solve_r<11>, ls_solve_r<12>, ls_solve_r<13>, ls_solve_r<14>,
                              ls_solve_r<15>};
 
-void ls_solve(const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt, const uint8_t *sub, int sel,
-              const double *Q, int r, int64_t n_out, double *Xout, hipStream_t st) {
+void ls_solve(Exec &ex, const int64_t *ptr, const int32_t *idx, const double *wt, const double *mt,
+              const uint8_t *sub, int sel, const double *Q, int r, int64_t n_out, double *Xout) {
   const int rt = (r + 1 + 15) / 16;
   const dim3 grid((unsigned)std::max<int64_t>(1, n_out));
+  const LsArgs a{ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout};
   if (rt == 1)
-    kLsByR[r](ptr, idx, wt, mt, sub, sel, Q, n_out, Xout, st);
+    kLsByR[r](ex, a);
   else if (rt == 2)
-    hipLaunchKernelGGL((ls_solve_kernel<2, 0>), grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    ex.run<LsArgs, ls_solve_body<2, 0>, 256, 1>(grid, dim3(256), a);
   else
-    hipLaunchKernelGGL((ls_solve_kernel<3, 0>), grid, dim3(256), 0, st, ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout);
+    ex.run<LsArgs, ls_solve_body<3, 0>, 256, 1>(grid, dim3(256), a);
+}
+
+void gaussian_block(Exec &ex, int64_t n, int p, uint64_t seed, double *Y) {
+  ex.run<GaussArgs, gaussian_block_body, 256>(dim3(cdiv(n * ((p + 3) / 4), 256)), dim3(256), GaussArgs{n, p, seed, Y});
+}
+
+void scale_cols(Exec &ex, double *U, int64_t n, int r, const double *s) {
+  ex.run<ScaleArgs, scale_cols_body, 256>(dim3(cdiv(n * r, 256)), dim3(256), ScaleArgs{U, n, r, s});
 }
 
 // U (n1 x r), V (n2 x r, orthonormal columns) -> canonical Uc, sigma, Vc
 // (U V^T = Uc diag(sigma) Vc^T). Uc written to Uout, Vc to Vout.
-void canonical(const Ws &w, const double *U, int64_t n1, const double *V, int64_t n2, int r, double *Uout,
-               double *Vout, double *sigma, hipStream_t st) {
-  jacobi_eig(w.part, gram(w, U, n1, r, st), r, r, w.Mu, w.Mv, sigma, st);
-  apply2(U, n1, w.Mu, Uout, nullptr, nullptr, V, n2, w.Mv, Vout, r, r, st);
-  hipLaunchKernelGGL(sign_fix_kernel, dim3(r), dim3(256), 0, st, Uout, n1, Vout, n2, r);
+void canonical(Exec &ex, const Ws &w, const double *U, int64_t n1, const double *V, int64_t n2, int r, double *Uout,
+               double *Vout, double *sigma) {
+  jacobi_eig(ex, w.part, gram(ex, w, U, n1, r), r, r, w.Mu, w.Mv, sigma);
+  apply2(ex, U, n1, w.Mu, Uout, nullptr, nullptr, V, n2, w.Mv, Vout, r, r);
+  ex.run<SignArgs, sign_fix_body, 256>(dim3(r), dim3(256), SignArgs{Uout, n1, Vout, n2, r});
 }
 
 }  // namespace
@@ -1111,23 +1283,24 @@ hipError_t svd_sketch_run(const float *At, const float *Bt, int64_t n1, int64_t 
   char *c = static_cast<char *>(wsbase) + carve_bytes(n1, n2, p, r);
   double *T = reinterpret_cast<double *>(c);
   double *tpart = reinterpret_cast<double *>(c + ((size_t)k * p * 8 + 255) / 256 * 256);
+  Exec ex(st);
   // block subspace iteration on X = At Bt^T (n1 x n2) from a Philox-seeded start
-  hipLaunchKernelGGL(gaussian_block_kernel, dim3(cdiv(n2 * ((p + 3) / 4), 256)), dim3(256), 0, st, n2, p, seed, w.Y);
-  orth(w, w.Y, n2, p, st);
+  gaussian_block(ex, n2, p, seed, w.Y);
+  orth(ex, w, w.Y, n2, p);
   for (int it = 0; it < iters; ++it) {
     lowrank_apply(Bt, n2, At, n1, k, w.Y, p, T, tpart, w.X, st);   // X = At (Bt^T Y)
-    orth(w, w.X, n1, p, st);
+    orth(ex, w, w.X, n1, p);
     lowrank_apply(At, n1, Bt, n2, k, w.X, p, T, tpart, w.Y, st);   // Y = Bt (At^T X)
-    orth(w, w.Y, n2, p, st);
+    orth(ex, w, w.Y, n2, p);
   }
   lowrank_apply(Bt, n2, At, n1, k, w.Y, p, T, tpart, w.X, st);
   // Rayleigh-Ritz: X^T X = W diag(lam) W^T; U = X W_r lam^-1/2, V = Y W_r, sigma = lam^1/2
-  jacobi_eig(w.part, gram(w, w.X, n1, p, st), p, r, w.Mu, w.Mv, w.sig, st);
-  apply2(w.X, n1, w.Mu, w.U, nullptr, nullptr, w.Y, n2, w.Mv, w.V, p, r, st);
-  hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
+  jacobi_eig(ex, w.part, gram(ex, w, w.X, n1, p), p, r, w.Mu, w.Mv, w.sig);
+  apply2(ex, w.X, n1, w.Mu, w.U, nullptr, nullptr, w.Y, n2, w.Mv, w.V, p, r);
+  scale_cols(ex, w.U, n1, r, w.sig);
   double *sig_out = sigma ? sigma : w.sig;
-  canonical(w, w.U, n1, w.V, n2, r, Uout, Vout, sig_out, st);
-  if (!sigma) hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, Uout, n1, r, sig_out);
+  canonical(ex, w, w.U, n1, w.V, n2, r, Uout, Vout, sig_out);
+  if (!sigma) scale_cols(ex, Uout, n1, r, sig_out);
   return hipGetLastError();
 }
 
@@ -1136,43 +1309,39 @@ size_t waltmin_ws_bytes(int64_t n1, int64_t n2, int r, int64_t /*nnz*/) {
   return carve_bytes(n1, n2, std::max(p, r), r);
 }
 
-hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *na2, double *Uout, double *Vout,
-                       double *sigma, void *wsbase, hipStream_t st, const double *fa_in) {
+static int waltmin_p(int64_t n1, int64_t n2, int r) {
+  return std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample)));
+}
+
+// Alg. 2 on one job's sample, its launches issued through `ex`; FA on the device.
+static void waltmin_body(Exec &ex, const smp_params &prm, const smp_omega &om, const float *na2, double *Uout,
+                         double *Vout, double *sigma, const Ws &w, const double *FA) {
   const int64_t n1 = om.n1, n2 = om.n2;
   const int r = prm.r, T = prm.T;
-  const int p = std::max(r, std::min<int>(kMaxP, (int)std::min<int64_t>(std::min(n1, n2), r + kInitOversample)));
+  const int p = waltmin_p(n1, n2, r);
   const int iters = prm.init_iters > 0 ? prm.init_iters : 2;
   const bool split = prm.omega_mode == SMP_OMEGA_SPLIT;
-  Ws w = carve_ws(wsbase, n1, n2, p, r);
   const uint8_t *scsr = split ? om.sub_csr : nullptr;
   const uint8_t *scsc = split ? om.sub_csc : nullptr;
 
-  // F_A (the squared Frobenius norm of A in the sampler's fixed order): given, or summed here
-  const double *FA = fa_in;
-  if (!FA) {
-    fixed_total(na2, n1, w.blocks, w.FA, st);
-    FA = w.FA;
-  }
-
   // ---- init: subspace iteration on R = w .* P_Omega0(M~)
-  hipLaunchKernelGGL(gaussian_block_kernel, dim3(cdiv(n2 * ((p + 3) / 4), 256)), dim3(256), 0, st, n2, p, prm.seed,
-                     w.Y);
+  gaussian_block(ex, n2, p, prm.seed, w.Y);
   // each sparse product applies the CholeskyQR map of its input (orth1_map)
-  orth1_map(w, w.Y, n2, p, st);
+  orth1_map(ex, w, w.Y, n2, p);
   for (int it = 0; it < iters; ++it) {
-    spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.M, w.X, st);
-    orth1_map(w, w.X, n1, p, st);
-    spmm(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 0, w.X, p, n2, w.M, w.Y, st);
-    if (it + 1 < iters) orth1_map(w, w.Y, n2, p, st);
+    spmm(ex, om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, w.M, w.X);
+    orth1_map(ex, w, w.X, n1, p);
+    spmm(ex, om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 0, w.X, p, n2, w.M, w.Y);
+    if (it + 1 < iters) orth1_map(ex, w, w.Y, n2, p);
   }
-  orth(w, w.Y, n2, p, st);
-  spmm(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, nullptr, w.X, st);
+  orth(ex, w, w.Y, n2, p);
+  spmm(ex, om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 0, w.Y, p, n1, nullptr, w.X);
   // Rayleigh-Ritz: X = R Y; X^T X = W diag(lam) W^T; U0 = X W_r lam^-1/2, V0 = Y W_r
-  jacobi_eig(w.part, gram(w, w.X, n1, p, st), p, r, w.Mu, w.Mv, w.sig, st);
-  apply2(w.X, n1, w.Mu, w.U, na2, FA, w.Y, n2, w.Mv, w.V, p, r, st);   // U0 (trimmed), V0
+  jacobi_eig(ex, w.part, gram(ex, w, w.X, n1, p), p, r, w.Mu, w.Mv, w.sig);
+  apply2(ex, w.X, n1, w.Mu, w.U, na2, FA, w.Y, n2, w.Mv, w.V, p, r);   // U0 (trimmed), V0
 
   if (T == 0) {
-    hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, w.U, n1, r, w.sig);
+    scale_cols(ex, w.U, n1, r, w.sig);
   } else {
     // Alg. 2 orthonormalises the fixed factor before each half-step. The
     // least-squares solution for the other factor only changes basis with it
@@ -1180,14 +1349,122 @@ hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *
     // orthonormalised once, before the last half-step, which also gives the
     // orthonormal V that the canonical form needs.
     for (int t = 0; t < T; ++t) {
-      ls_solve(om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 2 * t + 1, w.U, r, n2, w.V, st);
-      if (t + 1 == T) orth(w, w.V, n2, r, st);   // Q_V
-      ls_solve(om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 2 * t + 2, w.V, r, n1, w.U, st);
+      ls_solve(ex, om.col_ptr, om.row_idx, om.w_csc, om.mt_csc, scsc, 2 * t + 1, w.U, r, n2, w.V);
+      if (t + 1 == T) orth(ex, w, w.V, n2, r);   // Q_V
+      ls_solve(ex, om.row_ptr, om.col_idx, om.w_csr, om.mt_csr, scsr, 2 * t + 2, w.V, r, n1, w.U);
     }
   }
   double *sig_out = sigma ? sigma : w.sig;
-  canonical(w, w.U, n1, w.V, n2, r, Uout, Vout, sig_out, st);
-  if (!sigma) hipLaunchKernelGGL(scale_cols_kernel, dim3(cdiv(n1 * r, 256)), dim3(256), 0, st, Uout, n1, r, sig_out);
+  canonical(ex, w, w.U, n1, w.V, n2, r, Uout, Vout, sig_out);
+  if (!sigma) scale_cols(ex, Uout, n1, r, sig_out);
+}
+
+hipError_t waltmin_run(const smp_params &prm, const smp_omega &om, const float *na2, double *Uout, double *Vout,
+                       double *sigma, void *wsbase, hipStream_t st, const double *fa_in) {
+  const Ws w = carve_ws(wsbase, om.n1, om.n2, waltmin_p(om.n1, om.n2, prm.r), prm.r);
+  // F_A (the squared Frobenius norm of A in the sampler's fixed order): given, or summed here
+  const double *FA = fa_in;
+  if (!FA) {
+    fixed_total(na2, om.n1, w.blocks, w.FA, st);
+    FA = w.FA;
+  }
+  Exec ex(st);
+  waltmin_body(ex, prm, om, na2, Uout, Vout, sigma, w, FA);
+  return hipGetLastError();
+}
+
+// A group of WAltMin jobs: each job's launch sequence is recorded, the jobs
+// are bucketed by sequence (same kernels in the same order: same r, T,
+// initial iterations, subset mode and block-width class), and each bucket runs
+// as one launch per step over all its jobs, from per-step argument tables
+// copied to the device once (table_ws, waltmin_group_table_bytes bytes).
+// With graph != 0 the bucket's launches are captured into one HIP graph and
+// replayed once. Every job computes exactly what waltmin_run computes.
+size_t waltmin_group_table_bytes(int njobs, const smp_params *prm, const smp_omega *om) {
+  size_t total = 0;
+  for (int j = 0; j < njobs; ++j) {
+    std::vector<Op> ops;
+    Exec rec(&ops);
+    Ws w{};   // addresses are not used while recording sizes
+    smp_omega o = om[j];
+    waltmin_body(rec, prm[j], o, nullptr, nullptr, nullptr, nullptr, w, nullptr);
+    for (const Op &op : ops) total += (op.arg.size() + 15) / 16 * 16;
+  }
+  return total + 256;
+}
+
+hipError_t waltmin_group_run(int njobs, const smp_params *prm, const smp_omega *om, const float *const *na2,
+                             double *const *Uout, double *const *Vout, double *const *sigma, void *const *wsbase,
+                             const double *const *fa, void *table_ws, int graph, hipStream_t st) {
+  std::vector<std::vector<Op>> rec(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    const Ws w = carve_ws(wsbase[j], om[j].n1, om[j].n2, waltmin_p(om[j].n1, om[j].n2, prm[j].r), prm[j].r);
+    const double *FA = fa ? fa[j] : nullptr;
+    if (!FA) {   // F_A in the sampler's fixed order, one small launch per job before the group runs
+      fixed_total(na2[j], om[j].n1, w.blocks, w.FA, st);
+      FA = w.FA;
+    }
+    Exec ex(&rec[j]);
+    waltmin_body(ex, prm[j], om[j], na2[j], Uout[j], Vout[j], sigma ? sigma[j] : nullptr, w, FA);
+  }
+  // buckets of jobs with the same sequence of kernels
+  std::vector<std::vector<int>> buckets;
+  for (int j = 0; j < njobs; ++j) {
+    bool placed = false;
+    for (auto &b : buckets) {
+      const std::vector<Op> &a = rec[b[0]], &c = rec[j];
+      bool same = a.size() == c.size();
+      for (size_t i = 0; same && i < a.size(); ++i)
+        same = a[i].id == c[i].id && a[i].block.x == c[i].block.x && a[i].arg.size() == c[i].arg.size();
+      if (same) {
+        b.push_back(j);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) buckets.push_back({j});
+  }
+  // argument tables: bucket by bucket, step by step, job by job
+  std::vector<char> host;
+  std::vector<std::vector<size_t>> offs(buckets.size());
+  for (size_t bi = 0; bi < buckets.size(); ++bi) {
+    const auto &b = buckets[bi];
+    for (size_t i = 0; i < rec[b[0]].size(); ++i) {
+      offs[bi].push_back(host.size());
+      for (int j : b) host.insert(host.end(), rec[j][i].arg.begin(), rec[j][i].arg.end());
+      host.resize((host.size() + 15) / 16 * 16);
+    }
+  }
+  hipError_t e = hipMemcpyAsync(table_ws, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;   // the host tables are freed on return
+  char *dev = static_cast<char *>(table_ws);
+  // a graph is captured on a stream of its own when the caller's is the null stream
+  hipStream_t cs = st;
+  if (graph && !st && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return e;
+  for (size_t bi = 0; bi < buckets.size() && e == hipSuccess; ++bi) {
+    const auto &b = buckets[bi];
+    const std::vector<Op> &ops = rec[b[0]];
+    if (graph && (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) break;
+    for (size_t i = 0; i < ops.size(); ++i) {
+      unsigned gx = 1;
+      for (int j : b) gx = std::max(gx, rec[j][i].grid.x);
+      ops[i].launch(dev + offs[bi][i], dim3(gx, (unsigned)b.size()), ops[i].block, graph ? cs : st);
+    }
+    if (graph) {
+      hipGraph_t g = nullptr;
+      if ((e = hipStreamEndCapture(cs, &g)) != hipSuccess) break;
+      hipGraphExec_t ge = nullptr;
+      e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (e == hipSuccess) e = hipGraphLaunch(ge, cs);
+      const hipError_t e2 = hipStreamSynchronize(cs);
+      if (ge) hipGraphExecDestroy(ge);
+      hipGraphDestroy(g);
+      if (e == hipSuccess) e = e2;
+    }
+  }
+  if (cs != st) hipStreamDestroy(cs);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
