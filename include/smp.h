@@ -452,6 +452,21 @@ smp_status smp_solve_batch(int device, int njobs, const smp_params *p, const flo
                            const float *const *B, const int64_t *ldb, double *const *U, double *const *V,
                            double *const *sigma, int workers, size_t hbm_budget, smp_job_result *res);
 
+/* The same batch in two phases: `workers` threads (1..32), each with its own
+ * context and stream, run the sketch pass, the sample and the estimates of
+ * one job after another (each job's sample and estimates kept in memory of
+ * its own); then WAltMin runs for all jobs at once through smp_waltmin_group
+ * (graph != 0: one HIP graph per group of jobs with the same launch
+ * sequence). Each job's U, V, sigma are bit for bit those of smp_solve. The
+ * batch holds every job's sample until the end (about 40 B per sampled entry
+ * plus 4 n1 B per job); res[j].queue_ms is the wait before the job's first
+ * phase, run_ms from its start to the end of the grouped phase. Returns
+ * SMP_OK when every job succeeded, else the status of the first failed job. */
+smp_status smp_solve_batch_group(int device, int njobs, const smp_params *p, const float *const *A,
+                                 const int64_t *lda, const float *const *B, const int64_t *ldb, double *const *U,
+                                 double *const *V, double *const *sigma, int workers, int graph,
+                                 smp_job_result *res);
+
 #ifdef __cplusplus
 }
 #endif

@@ -140,6 +140,12 @@ EXPORTS = {
     "smp_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "smp_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SmpServerStats)]),
     "smp_server_destroy": (None, [ctypes.c_void_p]),
+    "smp_solve_batch_group": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(SmpParams),
+                                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                             ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(SmpJobResult)]),
     "smp_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(SmpParams),
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),

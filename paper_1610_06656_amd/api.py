@@ -447,6 +447,33 @@ def solve_batch(jobs, device=0, workers=4, hbm_budget=0):
     return st, [_job_dict(r) for r in res]
 
 
+def _batch_arrays(jobs):
+    n = len(jobs)
+    P = (SmpParams * n)(*[j["p"] for j in jobs])
+    vp = ctypes.c_void_p
+    A = (vp * n)(*[_ptr(j["A"], torch.float32, "A", dense=False) for j in jobs])
+    lda = (ctypes.c_int64 * n)(*[j["A"].stride(0) for j in jobs])
+    Bs = [j["B"] if j["B"] is not None else j["A"] for j in jobs]
+    B = (vp * n)(*[_ptr(b, torch.float32, "B", dense=False) for b in Bs])
+    ldb = (ctypes.c_int64 * n)(*[b.stride(0) for b in Bs])
+    U = (vp * n)(*[_ptr(j["U"], torch.float64, "U") for j in jobs])
+    V = (vp * n)(*[_ptr(j["V"], torch.float64, "V") for j in jobs])
+    S = (vp * n)(*[_ptr(j.get("sigma"), torch.float64, "sigma") for j in jobs])
+    return n, P, A, lda, B, ldb, U, V, S
+
+
+def solve_batch_group(jobs, device=0, workers=4, graph=True):
+    """smp_solve_batch_group over a list of jobs (keys as solve_batch): steps
+    2-4 on `workers` threads, then WAltMin for all jobs grouped. Returns the
+    per-job results and the batch status."""
+    lib = _lib.load()
+    n, P, A, lda, B, ldb, U, V, S = _batch_arrays(jobs)
+    res = (SmpJobResult * n)()
+    torch.cuda.current_stream().synchronize()
+    st = lib.smp_solve_batch_group(int(device), n, P, A, lda, B, ldb, U, V, S, int(workers), int(bool(graph)), res)
+    return st, [_job_dict(r) for r in res]
+
+
 def solve(A, B, k, r, T=10, m=None, seed=161006656, prec=_lib.SMP_PREC_FP32, omega_mode=_lib.SMP_OMEGA_REUSE,
           ctx=None, init_iters=0):
     """Alg. 1 on device tensors A (d x n1), B (d x n2, or None for A = B).

@@ -22,7 +22,7 @@ ARCH = os.environ.get("SMP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "server.cpp", "sketch.hip", "sketch_bf16.hip", "sketch_fp8.hip", "sketch_srht.hip", "sketch_sparse.hip", "sample.hip", "sample_multi.hip",
            "sort_scan.hip",
-           "estimate.hip", "waltmin.hip", "baselines.cpp", "tune.cpp"]
+           "estimate.hip", "waltmin.hip", "baselines.cpp", "tune.cpp", "batch_group.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

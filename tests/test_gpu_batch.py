@@ -210,3 +210,25 @@ def test_budget_bounds_memory_in_use(api):
     assert 2 <= st["max_running"] <= 3
     for j, (U, V, s) in zip(jobs, alone):
         assert torch.equal(j["out"][0], U) and torch.equal(j["out"][2], s)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_group_identical_to_each_job_alone(api, graph):
+    """smp_solve_batch_group (steps 2-4 on worker threads, WAltMin for all jobs
+    grouped) gives every job the bits of smp_solve, A = B and SPLIT jobs
+    included."""
+    jobs = [_make(api, i, j) for i, j in enumerate(JOBS)]
+    d, n1, n2, k, r, T = 3000, 150, 110, 60, 5, 6
+    A, B, Ad, Bd = latent(d, n1, n2, R=3, seed=SEED + 999)
+    p = api.make_params(d, n1, n2, k, r, T=T, seed=SEED + 998, omega_mode=api.SMP_OMEGA_SPLIT)
+    jobs.append(dict(p=p, A=Ad, B=Bd, out=[torch.empty(n1, r, dtype=torch.float64, device=DEV),
+                                          torch.empty(n2, r, dtype=torch.float64, device=DEV),
+                                          torch.empty(r, dtype=torch.float64, device=DEV)]))
+    alone = _alone(api, jobs)
+    batch = [dict(p=j["p"], A=j["A"], B=j["B"], U=j["out"][0], V=j["out"][1], sigma=j["out"][2]) for j in jobs]
+    st, res = api.solve_batch_group(batch, workers=3, graph=graph)
+    log(f"batch group: status {st}; workers {sorted({x['worker'] for x in res})}")
+    assert st == 0 and all(x["status"] == 0 for x in res)
+    for i, (j, ref) in enumerate(zip(jobs, alone)):
+        for a, b in zip(j["out"], ref):
+            assert torch.equal(a, b), f"job {i}"
