@@ -313,6 +313,29 @@ def run_mix(api, jobs, pools, large_pool, prec, workers, arrivals=None):
     return out
 
 
+def run_batch_group(api, jobs, pools, prec, workers, graph=True):
+    """The jobs through smp_solve_batch_group: steps 2-4 on worker threads,
+    then WAltMin for all jobs grouped."""
+    import torch
+    dev = pools[0][0].device
+    work, batch = [], []
+    for j in jobs:
+        A, B = pools[j["pool"]]
+        d, n, r = j["d"], j["n"], j["r"]
+        p = api.make_params(d, n, n, j["k"], r, T=10, seed=j["seed"], prec=prec)
+        outs = (torch.empty(n, r, dtype=torch.float64, device=dev), torch.empty(n, r, dtype=torch.float64, device=dev),
+                torch.empty(r, dtype=torch.float64, device=dev))
+        batch.append(dict(p=p, A=A[:d, :n], B=B[:d, :n], U=outs[0], V=outs[1], sigma=outs[2]))
+        work.append(8.0 * d * n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, res = api.solve_batch_group(batch, workers=workers, graph=graph)
+    wall = time.perf_counter() - t0
+    return {"jobs": len(jobs), "failed": sum(r["status"] != 0 for r in res), "wall_s": round(wall, 4),
+            "solves_per_s": round(len(jobs) / wall, 2), "input_gbps": round(sum(work) / wall / 1e9, 2),
+            "graph": bool(graph)}
+
+
 def mix_legs(api, args, pools, large_pool, dev):
     """The batching mix (512 jobs at once) and the serving mix (Poisson
     arrivals, 5% large jobs), each with BF16 and FP32 sketches."""
@@ -339,12 +362,18 @@ def mix_legs(api, args, pools, large_pool, dev):
             run_mix(api, jobs[:8], pools, large_pool, prec, args.workers)          # warm-up (workspaces, code)
             legs[leg] = run_mix(api, jobs, pools, large_pool, prec, args.workers, arr)
         legs["bf16_vs_fp32_solves"] = round(legs["bf16"]["solves_per_s"] / legs["fp32"]["solves_per_s"], 3)
+        if name == "batch":   # the same jobs with WAltMin grouped over all of them
+            for leg, prec in (("bf16", api.SMP_PREC_BF16), ("fp32", api.SMP_PREC_FP32)):
+                run_batch_group(api, jobs[:8], pools, prec, args.workers)          # warm-up
+                legs["group_" + leg] = run_batch_group(api, jobs, pools, prec, args.workers)
         out[name] = legs
     out["batch"]["workload"] = (f"{b['jobs']} independent jobs submitted at once: d uniform in [10k, 200k], n1 = n2 "
                                 f"uniform in [128, 2048], r in {{5, 10, 20}}, k = r * uniform{{4..20}}, T = 10, "
                                 f"m = 4nr ln n; latent rank 10, noise 0.1, column scale (j+1)^-0.5; each job's own "
                                 f"seed for Pi and the coins; inputs are top-left blocks of {b['pools']} resident "
-                                f"200000 x 2048 pairs; {args.workers} server workers")
+                                f"200000 x 2048 pairs; {args.workers} server workers (bf16, fp32) or {args.workers} "
+                                f"workers for steps 2-4 and WAltMin grouped over all jobs in one HIP graph per "
+                                f"group of equal launch sequences (group_bf16, group_fp32)")
     if "serve" in out:
         out["serve"]["workload"] = (f"Poisson arrivals at {sv['rate_per_s']:.0f} jobs/s for {args.serve_seconds:.1f} s "
                                     f"({len(arrivals)} jobs): the batching mix plus {100 * sv['large_frac']:.0f}% large "
@@ -374,6 +403,7 @@ def main_mix(args):
            "n_gpus": 1, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
            "config": {"workload": leg["workload"], "workers": args.workers}, "bf16": leg["bf16"], "fp32": leg["fp32"],
            "bf16_vs_fp32_solves": leg["bf16_vs_fp32_solves"]}
+    out.update({k: v for k, v in leg.items() if k.startswith("group_")})
     print(json.dumps(out), flush=True)
 
 

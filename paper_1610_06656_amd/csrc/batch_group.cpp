@@ -12,7 +12,9 @@
 // Every job's result is bit for bit what smp_solve gives for it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <mutex>
 #include <string>
@@ -43,10 +45,21 @@ struct Held {
     for (void *p : allocs) hipFree(p);
     allocs.clear();
   }
+  // the job's share of the batch arena (bytes at `at`, `left` of them free);
+  // a share too small (a sample beyond its bound) falls back to hipMalloc
+  char *at = nullptr;
+  size_t left = 0;
   template <typename T>
   T *alloc(int64_t count) {
+    const size_t b = ((size_t)std::max<int64_t>(1, count) * sizeof(T) + 255) / 256 * 256;
+    if (b <= left) {
+      T *out = reinterpret_cast<T *>(at);
+      at += b;
+      left -= b;
+      return out;
+    }
     void *p = nullptr;
-    if (hipMalloc(&p, (size_t)std::max<int64_t>(1, count) * sizeof(T)) != hipSuccess) {
+    if (hipMalloc(&p, b) != hipSuccess) {
       hipGetLastError();
       return nullptr;
     }
@@ -54,6 +67,20 @@ struct Held {
     return static_cast<T *>(p);
   }
 };
+
+// Bytes a job's sample, estimates and norms take at most (the bound on |Omega|
+// that smp_workspace_size uses): allocated once for the whole batch, since
+// hipMalloc per job would serialise the workers.
+size_t held_bytes(const smp_params &p) {
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const double m = p.m;
+  const int64_t cap = (int64_t)std::min<double>((double)p.n1 * (double)p.n2,
+                                                (p.flags & SMP_SAMPLE_MULTINOMIAL) ? (double)smp::mn_draw_bound(p.n1, m)
+                                                                                   : m + 6.0 * std::sqrt(m) + 64.0);
+  const bool split = p.omega_mode == SMP_OMEGA_SPLIT;
+  return al(p.n1 * 4) + al((p.n1 + 1) * 8) + al((p.n2 + 1) * 8) + 2 * al(cap * 4) + 4 * al(cap * 8) +
+         (split ? 2 * al(cap) : 0);
+}
 
 // Grows a worker's scratch buffer of sketches and norms.
 struct Scratch {
@@ -93,33 +120,36 @@ smp_status prepare(smp_ctx *ctx, Scratch &sc, const smp_params &p, const float *
   smp_status s = smp_sketch(ctx, &q, A, lda, same ? nullptr : B, ldb, At, same ? nullptr : Bt, h.na2,
                             same ? nullptr : nb2);
   if (s != SMP_OK) return s;
+  const float *nb = same ? h.na2 : nb2;
+  const bool split = q.omega_mode == SMP_OMEGA_SPLIT;
   smp_omega om{};
   om.n1 = n1;
   om.n2 = n2;
-  om.cap = 0;
   om.row_ptr = rp;
   om.col_ptr = cp;
-  const float *nb = same ? h.na2 : nb2;
-  s = smp_sample(ctx, &q, h.na2, nb, &om);   // counts |Omega| (no entries fit a capacity of 0)
-  if (s != SMP_OK && s != SMP_ERR_CAPACITY) return s;
-  const int64_t nnz = om.nnz;
-  const bool split = q.omega_mode == SMP_OMEGA_SPLIT;
-  om.cap = nnz;
-  om.col_idx = h.alloc<int32_t>(nnz);
-  om.row_idx = h.alloc<int32_t>(nnz);
-  om.w_csr = h.alloc<double>(nnz);
-  om.w_csc = h.alloc<double>(nnz);
-  om.mt_csr = h.alloc<double>(nnz);
-  om.mt_csc = h.alloc<double>(nnz);
-  om.sub_csr = split ? h.alloc<uint8_t>(nnz) : nullptr;
-  om.sub_csc = split ? h.alloc<uint8_t>(nnz) : nullptr;
-  if (!om.col_idx || !om.row_idx || !om.w_csr || !om.w_csc || !om.mt_csr || !om.mt_csc ||
-      (split && (!om.sub_csr || !om.sub_csc)))
-    return SMP_ERR_OUT_OF_MEMORY;
-  if (nnz > 0) {
+  auto carve_entries = [&](int64_t cap) {
+    om.cap = cap;
+    om.col_idx = h.alloc<int32_t>(cap);
+    om.row_idx = h.alloc<int32_t>(cap);
+    om.w_csr = h.alloc<double>(cap);
+    om.w_csc = h.alloc<double>(cap);
+    om.mt_csr = h.alloc<double>(cap);
+    om.mt_csc = h.alloc<double>(cap);
+    om.sub_csr = split ? h.alloc<uint8_t>(cap) : nullptr;
+    om.sub_csc = split ? h.alloc<uint8_t>(cap) : nullptr;
+    return om.col_idx && om.row_idx && om.w_csr && om.w_csc && om.mt_csr && om.mt_csc &&
+           (!split || (om.sub_csr && om.sub_csc));
+  };
+  // the rest of the job's share holds the entry arrays at the bound on |Omega|
+  const size_t per = 2 * 4 + 4 * 8 + (split ? 2 : 0);
+  if (!carve_entries((int64_t)(h.left / per > 2048 ? h.left / per - 2048 : 1))) return SMP_ERR_OUT_OF_MEMORY;
+  s = smp_sample(ctx, &q, h.na2, nb, &om);
+  if (s == SMP_ERR_CAPACITY) {   // beyond the bound: arrays of the exact size
+    const int64_t nnz = om.nnz;
+    if (!carve_entries(nnz)) return SMP_ERR_OUT_OF_MEMORY;
     s = smp_sample(ctx, &q, h.na2, nb, &om);
-    if (s != SMP_OK) return s;
   }
+  if (s != SMP_OK) return s;
   s = smp_estimate(ctx, &q, At, same ? At : Bt, h.na2, nb, &om);
   if (s != SMP_OK) return s;
   h.q = q;
@@ -141,6 +171,22 @@ smp_status smp_solve_batch_group(int device, int njobs, const smp_params *p, con
   if (workers > 32) workers = 32;
   std::vector<Held> held(njobs);
   const Clock::time_point t0 = Clock::now();
+  if (hipSetDevice(device) != hipSuccess) return SMP_ERR_DEVICE;
+  size_t arena_bytes = 0;
+  std::vector<size_t> share(njobs);
+  for (int j = 0; j < njobs; ++j) arena_bytes += (share[j] = held_bytes(p[j]));
+  void *arena = nullptr;
+  if (hipMalloc(&arena, std::max<size_t>(256, arena_bytes)) != hipSuccess) {
+    hipGetLastError();
+    arena = nullptr;   // every job then allocates its own
+  } else {
+    char *c = static_cast<char *>(arena);
+    for (int j = 0; j < njobs; ++j) {
+      held[j].at = c;
+      held[j].left = share[j];
+      c += share[j];
+    }
+  }
   std::atomic<int> next{0};
   std::vector<std::thread> th;
   for (int w = 0; w < std::min(workers, njobs); ++w) {
@@ -210,6 +256,7 @@ smp_status smp_solve_batch_group(int device, int njobs, const smp_params *p, con
     if (first == SMP_OK && held[j].status != SMP_OK) first = (smp_status)held[j].status;
     held[j].release();
   }
+  if (arena) hipFree(arena);
   return first;
 }
 
