@@ -859,10 +859,12 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
         bf[tt] = x;
         af[tt] = a < r ? we * x : 0.0;
       }
+      // G is symmetric: the tiles below the diagonal are never formed (the
+      // solve reads the upper triangle); the right-hand side sits in column r
 #pragma unroll
       for (int ta = 0; ta < RT; ++ta)
 #pragma unroll
-        for (int tb = 0; tb < RT; ++tb)
+        for (int tb = ta; tb < RT; ++tb)
           acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ta], bf[tb], acc[ta][tb], 0, 0, 0);
     }
   };
@@ -892,7 +894,7 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
 #pragma unroll
   for (int ta = 0; ta < RT; ++ta)
 #pragma unroll
-    for (int tb = 0; tb < RT; ++tb)
+    for (int tb = ta; tb < RT; ++tb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) Gme[(ta * 16 + 4 * j + ent) * D + tb * 16 + col] = acc[ta][tb][j];
   __syncthreads();
@@ -909,35 +911,41 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
     mx = fmax(mx, G[a * D + a]);
     tr += G[a * D + a];
   }
-  if constexpr (RT == 1) {
-    // r <= 15: the same steps with row i of the system in the registers of
+  if constexpr (RT <= 2) {
+    // r <= 31: the same steps with row i of the system in the registers of
     // lane i (pivots and solution entries broadcast with v_readlane); the
     // back substitution reads the columns of L through LDS once. Each pivot's
-    // reciprocal is taken once and multiplied (one division per column). The
-    // kernel is instantiated for each r (R = r), so every bound below is a
-    // compile-time constant and the unrolled loops carry no guards.
+    // reciprocal is taken once and multiplied (one division per column). For
+    // r <= 15 the kernel is instantiated per r (R = r: every bound below is a
+    // compile-time constant); for 16 <= r <= 31 the system is padded to 32
+    // rows with an identity block (diagonal max(G) so that its pivots pass the
+    // test; zero right-hand side), which leaves rows < r as they are.
     constexpr int RR = R > 0 ? R : D;
-    double l[RR], Lc[RR], dv[RR];
+    double l[RR];
     bool solved = false;
     double x = 0.0;
     for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
       const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
       const double tol = 1e-12 * (mx + shift);
+      const double pad = mx + shift;
 #pragma unroll
-      for (int k = 0; k < RR; ++k) l[k] = (t < RR && k < r) ? G[t * D + k] + (k == t ? shift : 0.0) : 0.0;
-      double y = t < RR ? G[t * D + r] : 0.0;
+      for (int k = 0; k < RR; ++k)
+        l[k] = (t < r && k < r) ? G[(t < k ? t : k) * D + (t < k ? k : t)] + (k == t ? shift : 0.0)
+                                : (t == k && t < RR ? pad : 0.0);
+      double y = t < r ? G[t * D + r] : 0.0;
+      double dv = 0.0;   // lane j: the reciprocal of pivot j
       bool ok = true;
 #pragma unroll
       for (int j = 0; j < RR; ++j) {
-        dv[j] = 0.0;
         if (ok) {
           const double piv = readlane_f64(l[j], j);
           if (!(piv > tol)) {
             ok = false;
           } else {
             const double d = sqrt(piv);
-            dv[j] = 1.0 / d;
-            l[j] = t == j ? d : (t > j ? l[j] * dv[j] : l[j]);
+            const double dj = 1.0 / d;
+            dv = t == j ? dj : dv;
+            l[j] = t == j ? d : (t > j ? l[j] * dj : l[j]);
 #pragma unroll
             for (int k = j + 1; k < RR; ++k) l[k] -= l[j] * readlane_f64(l[j], k);   // only k <= t is kept in lane t
           }
@@ -947,20 +955,18 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
       // forward: L y = h
 #pragma unroll
       for (int k = 0; k < RR; ++k) {
-        const double yk = readlane_f64(y, k) * dv[k];
+        const double yk = readlane_f64(y, k) * readlane_f64(dv, k);
         y = t == k ? yk : (t > k ? y - l[k] * yk : y);
       }
-      // backward: L^T x = y; lane t needs column t of L
+      // backward: L^T x = y; lane t reads column t of L from LDS
 #pragma unroll
       for (int k = 0; k < RR; ++k)
         if (t < RR && k <= t) L[t * 32 + k] = l[k];
       wsync();
 #pragma unroll
-      for (int k = 0; k < RR; ++k) Lc[k] = k > t ? L[k * 32 + t] : 0.0;
-#pragma unroll
       for (int k = RR - 1; k >= 0; --k) {
-        const double xk = readlane_f64(y, k) * dv[k];
-        y = t == k ? xk : (t < k ? y - Lc[k] * xk : y);
+        const double xk = readlane_f64(y, k) * readlane_f64(dv, k);
+        y = t == k ? xk : (t < k ? y - L[k * 32 + (t < k ? t : 0)] * xk : y);
       }
       x = y;
       solved = true;
@@ -968,13 +974,14 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
     if (t < r) Xout[o * r + t] = solved ? x : 0.0;
     return;
   }
+  // r = 32: the same steps on the system in LDS
   bool solved = false;
   for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
     const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
     const double tol = 1e-12 * (mx + shift);
-    for (int e = t; e < r * r; e += 64) {
+    for (int e = t; e < r * r; e += 64) {   // G from its upper triangle (the tiles formed)
       const int i = e / r, c = e % r;
-      L[i * 32 + c] = G[i * D + c] + ((i == c) ? shift : 0.0);
+      L[i * 32 + c] = G[(i < c ? i : c) * D + (i < c ? c : i)] + ((i == c) ? shift : 0.0);
     }
     if (t < r) hv[t] = G[t * D + r];
     wsync();
