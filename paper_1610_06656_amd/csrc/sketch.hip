@@ -295,11 +295,12 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   if (pl.pi_stored && rows > 0 && !pi_buf) return hipErrorInvalidValue;
   SkArgs g{};
   const int nct = pl.ncol_tile;
-  const int vb = 4 * pl.nv;   // bytes of one lane's vector load
+  const int ve = pl.vec_elems > 0 ? pl.vec_elems : pl.nv;
+  const int vb = 4 * ve;   // bytes of one lane's vector load
   // vector loads need an aligned base, a leading dimension and a column count
-  // that are multiples of nv
+  // that are multiples of the load width
   auto vec_ok = [&](const float *X, int64_t ld, int64_t n) {
-    return ld % pl.nv == 0 && n % pl.nv == 0 && ((uintptr_t)X % (vb > 16 ? 16 : vb)) == 0;
+    return ld % ve == 0 && n % ve == 0 && ((uintptr_t)X % (vb > 16 ? 16 : vb)) == 0;
   };
   g.a = SkMat{A, lda, n1, 0, (int)((n1 + nct - 1) / nct), (int)vec_ok(A, lda, n1)};
   if (B) {

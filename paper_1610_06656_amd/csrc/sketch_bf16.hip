@@ -477,6 +477,53 @@ __device__ __forceinline__ void mfma_step_stored(const v8bf (&b)[NV], const v4u 
 // issue and the landing under conditions, the compiler cannot prove that a
 // register set's previous loads have completed and waits for every load in
 // flight before reusing it, which serialises the prefetch.)
+// Paired 16-byte row loads (nv = 2). The two lanes 2j and 2j + 1 of a row
+// group cover four adjacent columns; the even lane loads those four columns
+// of the group's even rows, the odd lane of its odd rows, so that every load
+// is 16 bytes wide (half as many load instructions as one 8-byte load per
+// row, at the same bytes). Unpacking swaps the halves between the two lanes
+// (DPP quad permutation [1, 0, 3, 2]) and leaves each lane its own two
+// columns of all 8 rows, exactly the values the 8-byte loads give.
+struct PairAddr {
+  const float *base;   // row lbeg, column 0 (uniform)
+  uint32_t lane_off;   // (8 gq + parity) * ld + first of the pair's four columns
+  uint32_t ld;
+  uint32_t pcol;       // first of the pair's four columns (clamped into the matrix)
+  int64_t nrows;       // rows of the split
+};
+
+template <bool CLAMP>
+__device__ __forceinline__ void load_pair_step(const PairAddr &pa, int64_t rel, int gq, int par, v4f (&y)[4]) {
+  if (!CLAMP || rel + kStep <= pa.nrows) {   // uniform: the whole step is inside the split
+    const float *bs = pa.base + (size_t)rel * pa.ld;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = *reinterpret_cast<const v4f *>(bs + (size_t)(2 * i) * pa.ld + pa.lane_off);
+  } else {
+    const int64_t last = pa.nrows - 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = rel + 8 * gq + 2 * i + par;
+      y[i] = *reinterpret_cast<const v4f *>(pa.base + (r <= last ? r : last) * (int64_t)pa.ld + pa.pcol);
+    }
+  }
+}
+
+__device__ __forceinline__ float swap_pair(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ void unpack_pair_step(const v4f (&y)[4], int par, Row<2> (&x)[8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const float a = y[i][v], c = y[i][2 + v];
+      const float recv = swap_pair(par ? a : c);
+      x[2 * i][v] = par ? recv : a;
+      x[2 * i + 1][v] = par ? c : recv;
+    }
+}
+
 template <int NV, bool NORM, bool CLAMP>
 __device__ __forceinline__ void finish_rows_if(const Row<NV> (&x)[8], int64_t row, int64_t row_last, bool valid,
                                                v8bf (&b)[NV], float (&ksum)[NV], float (&kcmp)[NV]) {
@@ -513,11 +560,24 @@ __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &
   ra.ld = (uint32_t)w.ld;
   ra.lane_off = (uint32_t)(8 * gq) * ra.ld + (uint32_t)lcol;
   ra.nrows = w.lend - w.lbeg;
-  Row<NV> raw[D][8];
+  constexpr bool PAIR = VEC && NV == 2;   // paired 16-byte loads (the host then requires 4-element alignment)
+  const int par = lane & 1;
+  PairAddr pa;
+  if constexpr (PAIR) {
+    const int64_t pc = col - 2 * par;   // the even lane's column: the pair's first
+    pa.base = ra.base;
+    pa.ld = ra.ld;
+    pa.pcol = (uint32_t)(pc < w.n - 4 ? pc : w.n - 4);
+    pa.lane_off = (uint32_t)(8 * gq + par) * pa.ld + pa.pcol;
+    pa.nrows = ra.nrows;
+  }
+  Row<NV> raw[PAIR ? 1 : D][8];
+  v4f rawp[PAIR ? D : 1][4];
   v4u pst[D][CPW];
   v8bf b[NV];
   auto issue = [&](int set, int64_t t) {   // t < nsteps; every load is unconditional (see above)
-    load_step<NV, VEC, CLAMP>(w, ra, kStep * t, gq, lcol, raw[set]);
+    if constexpr (PAIR) load_pair_step<CLAMP>(pa, kStep * t, gq, par, rawp[set]);
+    else load_step<NV, VEC, CLAMP>(w, ra, kStep * t, gq, lcol, raw[set]);
     const v4u *src = pi + (blk0 + t) * fstride;
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
@@ -533,7 +593,13 @@ __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &
       const int i = wave + W * j;   // tiles mv .. LT-1 get zeros (the padding m-tiles stay zero)
       Ld[i * kPiUnit + lane] = (valid && i < mv) ? pst[set][j] : v4u{0u, 0u, 0u, 0u};
     }
-    finish_rows_if<NV, NORM, CLAMP>(raw[set], w.lbeg + kStep * t + 8 * gq, row_last, valid, b, ksum, kcmp);
+    if constexpr (PAIR) {
+      Row<NV> x[8];
+      unpack_pair_step(rawp[set], par, x);
+      finish_rows_if<NV, NORM, CLAMP>(x, w.lbeg + kStep * t + 8 * gq, row_last, valid, b, ksum, kcmp);
+    } else {
+      finish_rows_if<NV, NORM, CLAMP>(raw[set], w.lbeg + kStep * t + 8 * gq, row_last, valid, b, ksum, kcmp);
+    }
   };
 
 #pragma unroll
@@ -695,6 +761,7 @@ SketchPlan sketch_plan_bf16(int k, int cap_in) {
   p.pi_frag_bytes = kPiUnit * 16;
   p.mt_total = (k + 15) / 16;
   p.nv = nv;
+  p.vec_elems = nv == 2 ? 4 : nv;   // nv 2 loads 16 bytes per lane (paired rows)
   p.waves = waves;
   p.kc = kStep;
   p.kt = (p.mt_total + cap - 1) / cap;

@@ -50,6 +50,8 @@ struct SketchPlan {
   int pi_stored;        // 1: Pi is drawn window by window into a buffer that the pass streams
   int pi_rows;          // stored Pi: data rows per fragment block (32 BF16, 128 FP8)
   int pi_frag_bytes;    // stored Pi: bytes of one fragment (one MFMA A operand: 1024 BF16, 2048 FP8)
+  int vec_elems = 0;    // vector loads: the alignment (elements) of base, leading dimension and column count
+                        // they need (0: nv)
   int srht = 0;         // 1: the SRHT pass (sketch_srht.hip); mt holds its accumulators per thread
   int64_t d = 0;        // SRHT: rows of A and B (the Hadamard size is the next power of two)
 };
