@@ -477,13 +477,15 @@ __device__ __forceinline__ void mfma_step_stored(const v8bf (&b)[NV], const v4u 
 // issue and the landing under conditions, the compiler cannot prove that a
 // register set's previous loads have completed and waits for every load in
 // flight before reusing it, which serialises the prefetch.)
-// Paired 16-byte row loads (nv = 2). The two lanes 2j and 2j + 1 of a row
-// group cover four adjacent columns; the even lane loads those four columns
-// of the group's even rows, the odd lane of its odd rows, so that every load
-// is 16 bytes wide (half as many load instructions as one 8-byte load per
-// row, at the same bytes). Unpacking swaps the halves between the two lanes
-// (DPP quad permutation [1, 0, 3, 2]) and leaves each lane its own two
-// columns of all 8 rows, exactly the values the 8-byte loads give.
+// Paired 16-byte row loads (nv = 2). Lanes q and q + 8 of a row group
+// (q < 8) own the four adjacent columns 4q .. 4q + 3 of the wave's 32 (lane q
+// the first two, lane q + 8 the last two); lane q loads those four columns of
+// the group's even rows, lane q + 8 of its odd rows, so that every load is 16
+// bytes wide (half as many load instructions as one 8-byte load per row) and
+// lanes 0-7 and 8-15 each read one whole 128-byte line. Unpacking swaps the
+// halves between the two lanes (DPP rotation by 8 within the 16-lane row)
+// and leaves each lane its own two columns of all 8 rows, exactly the values
+// the 8-byte loads give.
 struct PairAddr {
   const float *base;   // row lbeg, column 0 (uniform)
   uint32_t lane_off;   // (8 gq + parity) * ld + first of the pair's four columns
@@ -509,7 +511,7 @@ __device__ __forceinline__ void load_pair_step(const PairAddr &pa, int64_t rel, 
 }
 
 __device__ __forceinline__ float swap_pair(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x128, 0xF, 0xF, false));
 }
 
 __device__ __forceinline__ void unpack_pair_step(const v4f (&y)[4], int par, Row<2> (&x)[8]) {
@@ -561,7 +563,7 @@ __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &
   ra.lane_off = (uint32_t)(8 * gq) * ra.ld + (uint32_t)lcol;
   ra.nrows = w.lend - w.lbeg;
   constexpr bool PAIR = VEC && NV == 2;   // paired 16-byte loads (the host then requires 4-element alignment)
-  const int par = lane & 1;
+  const int par = (lane >> 3) & 1;
   PairAddr pa;
   if constexpr (PAIR) {
     const int64_t pc = col - 2 * par;   // the even lane's column: the pair's first
@@ -629,7 +631,9 @@ __global__ __launch_bounds__(64 * W) void sketch_bf16_stored_kernel(SkArgs g) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int q = lane & 15, gq = lane >> 4;
-  const int64_t col = (int64_t)w.tile * (16 * W * NV) + wave * (16 * NV) + q * NV;
+  // the lane's NV columns (paired loads: lanes q and q + 8 own columns 4q .. 4q + 3 of the wave's 32)
+  constexpr bool PAIR = VEC && NV == 2;
+  const int64_t col = (int64_t)w.tile * (16 * W * NV) + wave * (16 * NV) + (PAIR ? (q & 7) * 4 + (q >> 3) * 2 : q * NV);
   const int i0 = w.kc * MT;
   const int mv = g.mt_total - i0 < MT ? g.mt_total - i0 : MT;
 
