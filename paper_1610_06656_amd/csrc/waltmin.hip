@@ -769,7 +769,8 @@ __device__ __forceinline__ void sign_fix_body(const SignArgs &a_) {
 // at once when RT = 1); the wave's next chunk's metadata is requested right
 // after the first batch of rows, so that the two loads overlap. The four waves'
 // Gram tiles are summed in LDS and the r x r system is solved there.
-// R > 0: the instantiation for r = R (RT = 1 only); R = 0: any r of the tile width.
+// R > 0: the register solve's row count (RT = 1: r = R; RT = 2: r <= R, padded);
+// R = 0: any r of the tile width (RT = 3, the solve in LDS).
 struct LsArgs {
   const int64_t *ptr;
   const int32_t *idx;
@@ -915,11 +916,12 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
     // r <= 31: the same steps with row i of the system in the registers of
     // lane i (pivots and solution entries broadcast with v_readlane); the
     // back substitution reads the columns of L through LDS once. Each pivot's
-    // reciprocal is taken once and multiplied (one division per column). For
-    // r <= 15 the kernel is instantiated per r (R = r: every bound below is a
-    // compile-time constant); for 16 <= r <= 31 the system is padded to 32
-    // rows with an identity block (diagonal max(G) so that its pivots pass the
-    // test; zero right-hand side), which leaves rows < r as they are.
+    // reciprocal is taken once and multiplied (one division per column). The
+    // kernel is instantiated for R rows (every bound below is a compile-time
+    // constant): R = r for r <= 15; for 16 <= r <= 31, R is r rounded up to a
+    // multiple of 4 and the system is padded to R rows with an identity block
+    // (diagonal max(G) so that its pivots pass the test; zero right-hand
+    // side), which leaves rows < r as they are.
     constexpr int RR = R > 0 ? R : D;
     double l[RR];
     bool solved = false;
@@ -1226,9 +1228,16 @@ void ls_solve(Exec &ex, const int64_t *ptr, const int32_t *idx, const double *wt
   const LsArgs a{ptr, idx, wt, mt, sub, sel, Q, r, n_out, Xout};
   if (rt == 1)
     kLsByR[r](ex, a);
-  else if (rt == 2)
-    ex.run<LsArgs, ls_solve_body<2, 0>, 256, 1>(grid, dim3(256), a);
-  else
+  else if (rt == 2) {   // the register solve padded to the next multiple of 4 rows
+    if (r <= 20)
+      ex.run<LsArgs, ls_solve_body<2, 20>, 256, 1>(grid, dim3(256), a);
+    else if (r <= 24)
+      ex.run<LsArgs, ls_solve_body<2, 24>, 256, 1>(grid, dim3(256), a);
+    else if (r <= 28)
+      ex.run<LsArgs, ls_solve_body<2, 28>, 256, 1>(grid, dim3(256), a);
+    else
+      ex.run<LsArgs, ls_solve_body<2, 32>, 256, 1>(grid, dim3(256), a);
+  } else
     ex.run<LsArgs, ls_solve_body<3, 0>, 256, 1>(grid, dim3(256), a);
 }
 
