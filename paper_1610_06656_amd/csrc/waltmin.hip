@@ -51,6 +51,19 @@ constexpr int kInitOversample = 5;
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)std::max<int64_t>(1, (a + b - 1) / b); }
 
 // Lane `src`'s value of v, in every lane.
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2, each of which squares the relative error (a
+// shorter dependent chain than a correctly rounded square root and division).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = __builtin_fma(-(x * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int src) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
@@ -795,8 +808,6 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
   constexpr int D = RT * 16;
   constexpr int BATCH = RT == 1 ? 16 : (RT == 2 ? 8 : 4);
   __shared__ double Gw[4 * D * D];
-  __shared__ double L[32 * 32];
-  __shared__ double hv[32];
   const int64_t o = blockIdx.x;
   if (o >= n_out) return;
   const int t = threadIdx.x;
@@ -944,8 +955,8 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
           if (!(piv > tol)) {
             ok = false;
           } else {
-            const double d = sqrt(piv);
-            const double dj = 1.0 / d;
+            const double dj = rsqrt_nr(piv);
+            const double d = piv * dj;
             dv = t == j ? dj : dv;
             l[j] = t == j ? d : (t > j ? l[j] * dj : l[j]);
 #pragma unroll
@@ -960,23 +971,26 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
         const double yk = readlane_f64(y, k) * readlane_f64(dv, k);
         y = t == k ? yk : (t > k ? y - l[k] * yk : y);
       }
-      // backward: L^T x = y; lane t reads column t of L from LDS
+      // backward: L^T x = y; lane t reads column t of L from LDS (the second
+      // wave's Gram area, free once the four partial Grams are summed)
+      double *Lr = Gw + D * D;
 #pragma unroll
       for (int k = 0; k < RR; ++k)
-        if (t < RR && k <= t) L[t * 32 + k] = l[k];
+        if (t < RR && k <= t) Lr[t * RR + k] = l[k];
       wsync();
 #pragma unroll
       for (int k = RR - 1; k >= 0; --k) {
         const double xk = readlane_f64(y, k) * readlane_f64(dv, k);
-        y = t == k ? xk : (t < k ? y - L[k * 32 + (t < k ? t : 0)] * xk : y);
+        y = t == k ? xk : (t < k ? y - Lr[k * RR + (t < k ? t : 0)] * xk : y);
       }
       x = y;
       solved = true;
     }
     if (t < r) Xout[o * r + t] = solved ? x : 0.0;
-    return;
-  }
+  } else {
   // r = 32: the same steps on the system in LDS
+  __shared__ double L[32 * 32];
+  __shared__ double hv[32];
   bool solved = false;
   for (int attempt = 0; attempt < 2 && mx > 0.0 && !solved; ++attempt) {
     const double shift = attempt == 0 ? 0.0 : 1e-9 * tr / r;
@@ -1027,6 +1041,7 @@ __device__ __forceinline__ void ls_solve_body(const LsArgs &a_) {
     solved = true;
   }
   if (t < r) Xout[o * r + t] = solved ? hv[t] : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------- host helpers
@@ -1230,13 +1245,13 @@ void ls_solve(Exec &ex, const int64_t *ptr, const int32_t *idx, const double *wt
     kLsByR[r](ex, a);
   else if (rt == 2) {   // the register solve padded to the next multiple of 4 rows
     if (r <= 20)
-      ex.run<LsArgs, ls_solve_body<2, 20>, 256, 1>(grid, dim3(256), a);
+      ex.run<LsArgs, ls_solve_body<2, 20>, 256, 4>(grid, dim3(256), a);
     else if (r <= 24)
-      ex.run<LsArgs, ls_solve_body<2, 24>, 256, 1>(grid, dim3(256), a);
+      ex.run<LsArgs, ls_solve_body<2, 24>, 256, 4>(grid, dim3(256), a);
     else if (r <= 28)
-      ex.run<LsArgs, ls_solve_body<2, 28>, 256, 1>(grid, dim3(256), a);
+      ex.run<LsArgs, ls_solve_body<2, 28>, 256, 4>(grid, dim3(256), a);
     else
-      ex.run<LsArgs, ls_solve_body<2, 32>, 256, 1>(grid, dim3(256), a);
+      ex.run<LsArgs, ls_solve_body<2, 32>, 256, 4>(grid, dim3(256), a);
   } else
     ex.run<LsArgs, ls_solve_body<3, 0>, 256, 1>(grid, dim3(256), a);
 }
