@@ -270,6 +270,9 @@ WALTMIN_CASES = {
     "r20_tiles": dict(d=3000, n=160, k=200, r=20, T=5, R=20),
     "split": dict(d=2000, n=200, k=100, r=4, T=2, split=True, mscale=6.0),
     "r28_wide": dict(d=3000, n=220, k=240, r=28, T=4, R=28),   # p = 33 columns in the initial subspace
+    # Gram columns past the first 16 summed on the VALU (r + 1 <= 25)
+    "r17_rem": dict(d=3000, n1=150, n2=190, k=200, r=17, T=4, R=17),
+    "r24_rem": dict(d=3000, n=210, k=240, r=24, T=4, R=24),
 }
 
 
