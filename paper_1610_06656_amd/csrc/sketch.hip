@@ -295,13 +295,13 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   if (pl.pi_stored && rows > 0 && !pi_buf) return hipErrorInvalidValue;
   SkArgs g{};
   const int nct = pl.ncol_tile;
-  const int ve = pl.vec_elems > 0 ? pl.vec_elems : pl.nv;
-  const int vb = 4 * ve;   // bytes of one lane's vector load
-  // vector loads need an aligned base, a leading dimension and a column count
-  // that are multiples of the load width
-  auto vec_ok = [&](const float *X, int64_t ld, int64_t n) {
-    return ld % ve == 0 && n % ve == 0 && ((uintptr_t)X % (vb > 16 ? 16 : vb)) == 0;
+  // vector loads of e elements per lane need an aligned base, a leading
+  // dimension and a column count that are multiples of e
+  auto aligned = [](const float *X, int64_t ld, int64_t n, int e) {
+    const int vb = 4 * e;
+    return ld % e == 0 && n % e == 0 && ((uintptr_t)X % (vb > 16 ? 16 : vb)) == 0;
   };
+  auto vec_ok = [&](const float *X, int64_t ld, int64_t n) { return aligned(X, ld, n, pl.nv); };
   g.a = SkMat{A, lda, n1, 0, (int)((n1 + nct - 1) / nct), (int)vec_ok(A, lda, n1)};
   if (B) {
     g.b = SkMat{B, ldb, n2, n1, (int)((n2 + nct - 1) / nct), (int)vec_ok(B, ldb, n2)};
@@ -359,9 +359,13 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
   // nwin windows of equal size (the first nblk mod nwin one block longer),
   // each one Pi draw plus one main launch; the first window's launch stores
   // the partials of a one-shot pass, every later one adds into them.
+  // the widest loads the inputs allow: vec_elems (paired 16-byte loads), nv, or scalar
   const bool vec = g.a.vec_ok && g.b.vec_ok;
-  KernelPtr kmain = reinterpret_cast<KernelPtr>(vec ? pl.kernel : pl.kernel_scalar);
-  KernelPtr ktail = reinterpret_cast<KernelPtr>(vec ? pl.kernel_clamp : pl.kernel_scalar);
+  const int ve = pl.vec_elems > pl.nv ? pl.vec_elems : pl.nv;
+  const bool wide = vec && (ve == pl.nv || (aligned(A, lda, n1, ve) && (!B || aligned(B, ldb, n2, ve))));
+  const bool narrow = vec && !wide && pl.kernel_v2 && pl.kernel_v2_clamp;
+  KernelPtr kmain = reinterpret_cast<KernelPtr>(wide ? pl.kernel : narrow ? pl.kernel_v2 : pl.kernel_scalar);
+  KernelPtr ktail = reinterpret_cast<KernelPtr>(wide ? pl.kernel_clamp : narrow ? pl.kernel_v2_clamp : pl.kernel_scalar);
   if (!kmain || !ktail) return hipErrorInvalidValue;
   const int64_t nblk = rows / pl.kc;
   const int64_t main_rows = nblk * pl.kc;

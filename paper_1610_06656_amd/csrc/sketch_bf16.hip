@@ -542,7 +542,7 @@ __device__ __forceinline__ void finish_rows_if(const Row<NV> (&x)[8], int64_t ro
   convert_step<NV>(x, b);
 }
 
-template <int MT, int NV, int G, int W, int D, bool VEC, bool CLAMP, bool NORM>
+template <int MT, int NV, int G, int W, int D, bool VEC, bool CLAMP, bool NORM, bool PAIRED>
 __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &w, int64_t col, int i0, int mv,
                                                  v4u *L, v4f (&acc)[MT][NV], float (&ksum)[NV], float (&kcmp)[NV]) {
   static_assert(D >= 2, "step t + 1 lands in another LDS buffer than the one step t reads");
@@ -562,7 +562,7 @@ __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &
   ra.ld = (uint32_t)w.ld;
   ra.lane_off = (uint32_t)(8 * gq) * ra.ld + (uint32_t)lcol;
   ra.nrows = w.lend - w.lbeg;
-  constexpr bool PAIR = VEC && NV == 2;   // paired 16-byte loads (the host then requires 4-element alignment)
+  constexpr bool PAIR = VEC && NV == 2 && PAIRED;   // paired 16-byte loads (the host then requires 4-element alignment)
   const int par = (lane >> 3) & 1;
   PairAddr pa;
   if constexpr (PAIR) {
@@ -621,7 +621,7 @@ __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &
   }
 }
 
-template <int MT, int NV, int G, int W, int D, bool VEC, bool CLAMP>
+template <int MT, int NV, int G, int W, int D, bool VEC, bool CLAMP, bool PAIRED>
 __global__ __launch_bounds__(64 * W) void sketch_bf16_stored_kernel(SkArgs g) {
   constexpr int LT = (MT + W - 1) / W * W;
   __shared__ __attribute__((aligned(16))) v4u L[D * LT * kPiUnit];
@@ -632,7 +632,7 @@ __global__ __launch_bounds__(64 * W) void sketch_bf16_stored_kernel(SkArgs g) {
   const int wave = tid >> 6, lane = tid & 63;
   const int q = lane & 15, gq = lane >> 4;
   // the lane's NV columns (paired loads: lanes q and q + 8 own columns 4q .. 4q + 3 of the wave's 32)
-  constexpr bool PAIR = VEC && NV == 2;
+  constexpr bool PAIR = VEC && NV == 2 && PAIRED;
   const int64_t col = (int64_t)w.tile * (16 * W * NV) + wave * (16 * NV) + (PAIR ? (q & 7) * 4 + (q >> 3) * 2 : q * NV);
   const int i0 = w.kc * MT;
   const int mv = g.mt_total - i0 < MT ? g.mt_total - i0 : MT;
@@ -647,37 +647,44 @@ __global__ __launch_bounds__(64 * W) void sketch_bf16_stored_kernel(SkArgs g) {
   for (int v = 0; v < NV; ++v) ksum[v] = kcmp[v] = 0.0f;
 
   if (w.lbeg < w.lend) {
-    if (w.kc == 0) loop_bf16_stored<MT, NV, G, W, D, VEC, CLAMP, true>(g, w, col, i0, mv, L, acc, ksum, kcmp);
-    else loop_bf16_stored<MT, NV, G, W, D, VEC, CLAMP, false>(g, w, col, i0, mv, L, acc, ksum, kcmp);
+    if (w.kc == 0) loop_bf16_stored<MT, NV, G, W, D, VEC, CLAMP, true, PAIRED>(g, w, col, i0, mv, L, acc, ksum, kcmp);
+    else loop_bf16_stored<MT, NV, G, W, D, VEC, CLAMP, false, PAIRED>(g, w, col, i0, mv, L, acc, ksum, kcmp);
   }
   sk_epilogue<MT, NV>(g, w, col, i0 * 16, gq, acc, ksum, kcmp);
 }
 
+// t, tc: vector loads (paired 16-byte loads at nv = 2), whole blocks and
+// clamped; t2, tc2: one nv-wide vector load per row (inputs aligned to nv but
+// not to 4 elements); ts: guarded scalar loads.
 template <int NV, int G, int W, int D, int MT, int MT0>
 struct KTabS {
-  static void fill(KernelPtr *t, KernelPtr *tc, KernelPtr *ts) {
-    t[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, false>;
-    tc[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, true>;
-    ts[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, false, true>;
-    KTabS<NV, G, W, D, MT - 1, MT0>::fill(t, tc, ts);
+  static void fill(KernelPtr *t, KernelPtr *tc, KernelPtr *ts, KernelPtr *t2, KernelPtr *tc2) {
+    t[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, false, true>;
+    tc[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, true, true>;
+    ts[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, false, true, true>;
+    if constexpr (NV == 2) {
+      t2[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, false, false>;
+      tc2[MT] = sketch_bf16_stored_kernel<MT, NV, G, W, D, true, true, false>;
+    }
+    KTabS<NV, G, W, D, MT - 1, MT0>::fill(t, tc, ts, t2, tc2);
   }
 };
 template <int NV, int G, int W, int D, int MT0>
 struct KTabS<NV, G, W, D, MT0, MT0> {
-  static void fill(KernelPtr *, KernelPtr *, KernelPtr *) {}
+  static void fill(KernelPtr *, KernelPtr *, KernelPtr *, KernelPtr *, KernelPtr *) {}
 };
 
 struct ShapeS {
   int nv, waves, depth, max_mt;
-  KernelPtr t[33], tc[33], ts[33];
+  KernelPtr t[33], tc[33], ts[33], t2[33], tc2[33];
 };
 
 ShapeS *shapes_stored(int &count) {
   // nv 2, 8 waves (two per SIMD), up to 16 m-tiles: 256 columns x 256 sketch
   // rows, 242 VGPRs at 16 m-tiles
-  static ShapeS tabs[] = {{2, 8, 2, 16, {}, {}, {}}};
+  static ShapeS tabs[] = {{2, 8, 2, 16, {}, {}, {}, {}, {}}};
   static const bool init = [] {
-    KTabS<2, 2, 8, 2, 16, 0>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts);
+    KTabS<2, 2, 8, 2, 16, 0>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts, tabs[0].t2, tabs[0].tc2);
     return true;
   }();
   (void)init;
@@ -690,7 +697,11 @@ KernelPtr bf16_stored_kernel_for(int nv, int waves, int depth, int mt, int varia
   ShapeS *t = shapes_stored(count);
   for (int i = 0; i < count; ++i)
     if (t[i].nv == nv && t[i].waves == waves && t[i].depth == depth && mt >= 1 && mt <= t[i].max_mt && t[i].t[mt])
-      return variant == 0 ? t[i].t[mt] : variant == 1 ? t[i].tc[mt] : t[i].ts[mt];
+      return variant == 0   ? t[i].t[mt]
+             : variant == 1 ? t[i].tc[mt]
+             : variant == 2 ? t[i].ts[mt]
+             : variant == 3 ? t[i].t2[mt]
+                            : t[i].tc2[mt];
   return nullptr;
 }
 
@@ -775,6 +786,10 @@ SketchPlan sketch_plan_bf16(int k, int cap_in) {
   p.kernel = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 0));
   p.kernel_clamp = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 1));
   p.kernel_scalar = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 2));
+  if (p.vec_elems > nv) {
+    p.kernel_v2 = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 3));
+    p.kernel_v2_clamp = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 4));
+  }
   return p;
 }
 

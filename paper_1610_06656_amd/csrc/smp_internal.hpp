@@ -52,6 +52,8 @@ struct SketchPlan {
   int pi_frag_bytes;    // stored Pi: bytes of one fragment (one MFMA A operand: 1024 BF16, 2048 FP8)
   int vec_elems = 0;    // vector loads: the alignment (elements) of base, leading dimension and column count
                         // they need (0: nv)
+  void *kernel_v2 = nullptr;        // vec_elems > nv: the variants with one nv-wide load per row, for
+  void *kernel_v2_clamp = nullptr;  // inputs aligned to nv but not to vec_elems
   int srht = 0;         // 1: the SRHT pass (sketch_srht.hip); mt holds its accumulators per thread
   int64_t d = 0;        // SRHT: rows of A and B (the Hadamard size is the next power of two)
 };

@@ -77,6 +77,7 @@ SKETCH_CASES = {
     "k2000_wide_chunks": dict(d=1500, n1=90, n2=41, k=2000),
     "tiny": dict(d=3, n1=1, n2=5, k=1),
     "one_block_tail": dict(d=130, n1=513, n2=2, k=81),
+    "even_not_quad": dict(d=3000, n1=258, n2=130, k=400),   # n even, not a multiple of 4: 8-byte row loads
 }
 
 
