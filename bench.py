@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--no-errors", action="store_true", help="skip the spectral errors (profiling runs)")
     ap.add_argument("--workers", type=int, default=4, help="server worker threads (batch, serve)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window of the serve workload")
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0,
+                    help="HBM budget of the serve workload's server (GB of workspace, inputs and outputs of the "
+                         "running jobs; 0: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 2^30 bytes (the reference dispatch for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -258,9 +261,10 @@ def _pools(spec, count, d, n, seed, dev):
             for i in range(count)]
 
 
-def run_mix(api, jobs, pools, large_pool, prec, workers, arrivals=None):
-    """Run the jobs through one server; arrivals (seconds from start) or all
-    at once. Returns timing and latency figures."""
+def run_mix(api, jobs, pools, large_pool, prec, workers, arrivals=None, budget=0):
+    """Run the jobs through one server (admission within `budget` bytes, 0:
+    none); arrivals (seconds from start) or all at once. Returns timing and
+    latency figures."""
     import threading
 
     import torch
@@ -274,7 +278,7 @@ def run_mix(api, jobs, pools, large_pool, prec, workers, arrivals=None):
                 torch.empty(r, dtype=torch.float64, device=dev))
         work.append((p, A[:d, :n], B[:d, :n], outs, 8.0 * d * n, j["large"]))
     torch.cuda.synchronize()
-    srv = api.Server(0, workers=workers)
+    srv = api.Server(0, workers=workers, hbm_budget=int(budget))
     ids = [None] * len(work)
     results = [None] * len(work)
 
@@ -305,6 +309,9 @@ def run_mix(api, jobs, pools, large_pool, prec, workers, arrivals=None):
            "run_ms": {"p50": round(pct([r["run_ms"] for r in results], 50), 3),
                       "p99": round(pct([r["run_ms"] for r in results], 99), 3)},
            "max_running": st["max_running"]}
+    if budget:
+        out["hbm_budget_gb"] = round(budget / 1e9, 1)
+        out["max_in_use_gb"] = round(st["max_budget_in_use"] / 1e9, 2)
     big = [l for l, w in zip(lat, work) if w[5]]
     if big:
         small = [l for l, w in zip(lat, work) if not w[5]]
@@ -358,9 +365,10 @@ def mix_legs(api, args, pools, large_pool, dev):
         if name == "serve" and large_pool is None:
             continue
         legs = {}
+        budget = args.serve_budget_gb * 1e9 if name == "serve" else 0
         for leg, prec in (("bf16", api.SMP_PREC_BF16), ("fp32", api.SMP_PREC_FP32)):
             run_mix(api, jobs[:8], pools, large_pool, prec, args.workers)          # warm-up (workspaces, code)
-            legs[leg] = run_mix(api, jobs, pools, large_pool, prec, args.workers, arr)
+            legs[leg] = run_mix(api, jobs, pools, large_pool, prec, args.workers, arr, budget)
         legs["bf16_vs_fp32_solves"] = round(legs["bf16"]["solves_per_s"] / legs["fp32"]["solves_per_s"], 3)
         if name == "batch":   # the same jobs with WAltMin grouped over all of them
             for leg, prec in (("bf16", api.SMP_PREC_BF16), ("fp32", api.SMP_PREC_FP32)):
@@ -378,7 +386,9 @@ def mix_legs(api, args, pools, large_pool, dev):
         out["serve"]["workload"] = (f"Poisson arrivals at {sv['rate_per_s']:.0f} jobs/s for {args.serve_seconds:.1f} s "
                                     f"({len(arrivals)} jobs): the batching mix plus {100 * sv['large_frac']:.0f}% large "
                                     f"jobs (d = 1M, n1 = n2 = 4096, r = 20, k = r * uniform{{4..20}}; the large "
-                                    f"workload's matrices); {args.workers} server workers")
+                                    f"workload's matrices); {args.workers} server workers, admission within an HBM "
+                                    f"budget of {args.serve_budget_gb:.0f} GB (each running job's workspace, inputs "
+                                    f"and outputs)")
     return out
 
 
