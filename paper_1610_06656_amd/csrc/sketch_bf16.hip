@@ -222,6 +222,24 @@ __device__ __forceinline__ void load_step(const SkWork &w, const RowAddr &ra, in
   }
 }
 
+// Unaligned inputs: one 4-byte load per value from a clamped row and column,
+// all unconditional (a row past the split reads its last row, whose Pi
+// entries are zero there and which the norms leave out; a column past n reads
+// column n - 1 into an accumulator that is never stored). Offsets are 32-bit
+// from the split's first row (the host keeps every split below 2^31 elements).
+template <int NV>
+__device__ __forceinline__ void load_step_clamped(const RowAddr &ra, int64_t rel, int gq, const uint32_t (&c)[NV],
+                                                  Row<NV> (&x)[8]) {
+  const int64_t last = ra.nrows - 1;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t r = rel + 8 * gq + e;
+    const uint32_t ro = (uint32_t)(r <= last ? r : last) * ra.ld;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[e][v] = ra.base[ro + c[v]];
+  }
+}
+
 // One K step of a block, software-pipelined: issue the loads of the next
 // step, generate this step's share of the next block's Pi, multiply this
 // step (its rows were converted at the end of the previous step), then
@@ -573,13 +591,17 @@ __device__ __forceinline__ void loop_bf16_stored(const SkArgs &g, const SkWork &
     pa.lane_off = (uint32_t)(8 * gq + par) * pa.ld + pa.pcol;
     pa.nrows = ra.nrows;
   }
+  uint32_t ccol[NV];   // unaligned inputs: the lane's columns, clamped into the matrix
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ccol[v] = (uint32_t)(col + v < w.n ? col + v : w.n - 1);
   Row<NV> raw[PAIR ? 1 : D][8];
   v4f rawp[PAIR ? D : 1][4];
   v4u pst[D][CPW];
   v8bf b[NV];
   auto issue = [&](int set, int64_t t) {   // t < nsteps; every load is unconditional (see above)
     if constexpr (PAIR) load_pair_step<CLAMP>(pa, kStep * t, gq, par, rawp[set]);
-    else load_step<NV, VEC, CLAMP>(w, ra, kStep * t, gq, lcol, raw[set]);
+    else if constexpr (VEC) load_step<NV, VEC, CLAMP>(w, ra, kStep * t, gq, lcol, raw[set]);
+    else load_step_clamped<NV>(ra, kStep * t, gq, ccol, raw[set]);
     const v4u *src = pi + (blk0 + t) * fstride;
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
