@@ -90,7 +90,9 @@ SketchPlan plan_for(const smp_params *p) {
     pl.d = p->d;
     return pl;
   }
-  return smp::sketch_plan(p->k, p->prec);
+  SketchPlan pl = smp::sketch_plan(p->k, p->prec);
+  pl.ntot = p->n1 + p->n2;   // the FP8 fragment pass sizes its window by the columns
+  return pl;
 }
 
 // Rows one launch covers: one stored-Pi window, else all d rows.

@@ -292,6 +292,8 @@ hipError_t sketch_push(const SketchPlan &pl, const float *A, int64_t lda, int64_
                        float *part, double *npart, void *pi_buf, hipStream_t st) {
   if (rows < 0) return hipErrorInvalidValue;
   if (pl.srht) return srht_push(pl, A, lda, n1, B, ldb, n2, pl.d, row0, rows, k, seed, S, accumulate, part, npart, st);
+  if (pl.frag)
+    return fp8_frag_push(pl, A, lda, n1, B, ldb, n2, rows, k, seed, row0, S, accumulate, part, npart, pi_buf, st);
   if (pl.pi_stored && rows > 0 && !pi_buf) return hipErrorInvalidValue;
   SkArgs g{};
   const int nct = pl.ncol_tile;
@@ -407,6 +409,7 @@ static int64_t pi_row_bytes(const SketchPlan &pl) { return (int64_t)pl.mt_total 
 
 int64_t pi_window_rows(const SketchPlan &pl) {
   if (!pl.pi_stored) return 0;
+  if (pl.frag) return fp8_frag_window_rows(pl);
   int64_t cap = kPiWindowBytes;
   if (const char *e = getenv("SMP_PI_WINDOW_MB")) {   // tuning override
     const long v = strtol(e, nullptr, 10);
@@ -418,6 +421,7 @@ int64_t pi_window_rows(const SketchPlan &pl) {
 
 size_t sketch_pi_bytes(const SketchPlan &pl, int64_t rows) {
   if (!pl.pi_stored || rows <= 0) return 0;
+  if (pl.frag) return fp8_frag_bytes(pl, rows);
   const int64_t wr = std::min<int64_t>((rows + pl.pi_rows - 1) / pl.pi_rows * pl.pi_rows, pi_window_rows(pl));
   return (size_t)(wr / pl.pi_rows) * (size_t)pl.mt_total * (size_t)pl.pi_frag_bytes;
 }

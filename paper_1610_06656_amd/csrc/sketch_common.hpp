@@ -27,6 +27,12 @@ struct SkArgs {
   int accumulate;   // 1: add into the partials (streaming pushes); 0: store them (one-shot pass)
   uint64_t seed;
   const void *pi;   // stored-Pi passes: the fragments of the launch's first 32-row block (else null)
+  // FP8 fragment pass: the data as MFMA B operands (2 KiB per 128-row block and
+  // 16-column n-tile, blocks from the launch's first row), their E8M0 scales
+  // (64 B per block and n-tile) and the n-tile counts (A's, then B's)
+  const void *dfrag;
+  const uint8_t *dscale;
+  int nt16, ntA16;
   float *part;      // [S][ntot][kpad]
   double *npart;    // [S][ntot]
 };
@@ -123,7 +129,9 @@ __device__ __forceinline__ void kahan_add(float &sum, float &comp, float term) {
 // Split-K epilogue. acc[i][v] holds, in lane (q, ph), the sketch rows
 // c0 + 16 i + 4 ph + (0..3) of data column col + v (the 16x16 MFMA output
 // layout). Partial norms come from the sketch-row chunk 0 workgroup only.
-template <int MT, int NV>
+// Column v of the lane is col + VS * v. NORMS = false leaves the norm
+// partials alone (a pass whose norms come from elsewhere).
+template <int MT, int NV, int VS = 1, bool NORMS = true>
 __device__ __forceinline__ void sk_epilogue(const SkArgs &g, const SkWork &w, int64_t col, int c0, int ph,
                                             const v4f (&acc)[MT][NV], const float (&ksum)[NV],
                                             const float (&kcmp)[NV]) {
@@ -133,8 +141,8 @@ __device__ __forceinline__ void sk_epilogue(const SkArgs &g, const SkWork &w, in
     double nrm = (double)ksum[v] - (double)kcmp[v];
     nrm += __shfl_xor(nrm, 16, 64);
     nrm += __shfl_xor(nrm, 32, 64);
-    const int64_t c_ = col + v;
-    if (c_ < w.n && ph == 0 && w.kc == 0) {
+    const int64_t c_ = col + VS * v;
+    if (NORMS && c_ < w.n && ph == 0 && w.kc == 0) {
       double *dst = g.npart + (int64_t)(g.s_base + w.s) * g.ntot + w.col_base + c_;
       *dst = g.accumulate ? *dst + nrm : nrm;
     }
@@ -144,7 +152,7 @@ __device__ __forceinline__ void sk_epilogue(const SkArgs &g, const SkWork &w, in
     if (mt0 + i < g.mt_total) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const int64_t c_ = col + v;
+        const int64_t c_ = col + VS * v;
         if (c_ < w.n) {
           float *dst = g.part + ((int64_t)(g.s_base + w.s) * g.ntot + w.col_base + c_) * g.kpad + c0 + 16 * i + 4 * ph;
           float4 val = make_float4(acc[i][v][0], acc[i][v][1], acc[i][v][2], acc[i][v][3]);

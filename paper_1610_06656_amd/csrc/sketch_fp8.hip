@@ -461,6 +461,283 @@ __global__ __launch_bounds__(512) void sketch_fp8_stored_kernel(SkArgs g) {
 
 using KernelPtr = void (*)(SkArgs);
 
+// ---------------------------------------------------------------------------
+// Fragment pass (the default). The stored-Pi pass above reads the FP32 data
+// once per sketch-row chunk (4 bytes per value each time) and converts it in
+// every chunk; here each window of rows is first quantised once, by a
+// streaming kernel, into the B operands of v_mfma_scale_f32_16x16x128_f8f6f4
+// (E4M3 bytes in the operand's lane order, 2 KiB per 128-row block and
+// 16-column n-tile, stored as two 1 KiB halves: bytes 0-15 of every lane,
+// then bytes 16-31, so that the quantiser writes whole lines and the GEMM
+// reads 1 KiB per load instruction) with their E8M0 scales (the same per column and 32-row
+// block as above) and the columns' squared norms; the GEMM then reads one
+// byte per value per chunk with 16-byte loads, and its tiles hold 2 n-tiles
+// per wave (256 columns per workgroup) and up to 16 m-tiles.
+
+struct QArgs {
+  const float *A, *B;   // the window's first row (B null: A only)
+  int64_t lda, ldb, n1, n2;
+  int64_t rows;         // rows of the window; rows past them (to the last whole block) quantise as zeros
+  int nblk;             // 128-row blocks of the window
+  int nt16, ntA16;      // n-tiles in all (A's first, then B's) and A's
+  int rq;               // 32-row blocks per thread
+  uint8_t *frag;        // [nblk][nt16][2 halves][64 lanes][16 B]
+  uint8_t *scale;       // [nblk][nt16][64 lanes]
+  double *nscr;         // [gridDim.y][nt16 * 16] squared norms of the thread's rows
+};
+
+// Thread: one column (of the n-tile space, A's then B's) and rq consecutive
+// 32-row blocks. Block j (rows 32 j .. 32 j + 31) is 32-row block gp = j % 4
+// of 128-row block j / 4, i.e. K indices 32 gp + i of the operand: its rows
+// i < 16 are bytes 16 (gp / 2) + i of lane (q, 2 (gp % 2)) (half gp / 2 of
+// the fragment), rows i >= 16 the same bytes of lane (q, 2 (gp % 2) + 1), and
+// its scale is the byte of lane (q, gp). Loads are unconditional (clamped row
+// and column, masked after).
+__global__ __launch_bounds__(256) void quantize_fp8_kernel(QArgs a) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= (int64_t)a.nt16 * 16) return;
+  const int nt = (int)(c >> 4), q = (int)(c & 15);
+  const bool isb = nt >= a.ntA16;
+  const int64_t mc = isb ? c - (int64_t)a.ntA16 * 16 : c;
+  const int64_t nm = isb ? a.n2 : a.n1;
+  const bool cv = mc < nm;
+  const float *X = isb ? a.B : a.A;
+  const int64_t ld = isb ? a.ldb : a.lda;
+  const float *xc = X + (cv ? mc : nm - 1);
+  const int64_t last = a.rows - 1;
+  const int j0 = (int)blockIdx.y * a.rq;
+  const int j1 = j0 + a.rq < 4 * a.nblk ? j0 + a.rq : 4 * a.nblk;
+  double s2 = 0.0;
+  // block j + 1's rows are requested before block j is converted
+  float xn[32];
+  auto load = [&](int j, float (&x)[32]) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int64_t r = (int64_t)j * 32 + i;
+      x[i] = xc[(r <= last ? r : last) * ld];
+    }
+  };
+  if (j0 < j1) load(j0, xn);
+  for (int j = j0; j < j1; ++j) {
+    float x[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) x[i] = xn[i];
+    load(j + 1 < j1 ? j + 1 : j, xn);
+    float amax = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const bool ok = cv && (int64_t)j * 32 + i <= last;
+      x[i] = ok ? x[i] : 0.0f;
+      amax = __builtin_fmaxf(amax, __builtin_fabsf(x[i]));
+      s2 = __builtin_fma((double)x[i], (double)x[i], s2);
+    }
+    const int ex = scale_exp(amax);
+    uint32_t wv[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h)
+      wv[h] = (uint32_t)cvt4(__builtin_amdgcn_ldexpf(x[4 * h], -ex), __builtin_amdgcn_ldexpf(x[4 * h + 1], -ex),
+                             __builtin_amdgcn_ldexpf(x[4 * h + 2], -ex), __builtin_amdgcn_ldexpf(x[4 * h + 3], -ex));
+    const int blk = j >> 2, gp = j & 3;
+    const int64_t fb = (int64_t)blk * a.nt16 + nt;
+    uint8_t *f = a.frag + fb * 2048 + 1024 * (gp >> 1);
+    const int g0 = 2 * (gp & 1);
+    *reinterpret_cast<v4u8 *>(f + (16 * g0 + q) * 16) = v4u8{wv[0], wv[1], wv[2], wv[3]};
+    *reinterpret_cast<v4u8 *>(f + (16 * (g0 + 1) + q) * 16) = v4u8{wv[4], wv[5], wv[6], wv[7]};
+    a.scale[fb * 64 + 16 * gp + q] = (uint8_t)(ex + 127);
+  }
+  a.nscr[(int64_t)blockIdx.y * a.nt16 * 16 + c] = s2;
+}
+
+// The window's squared norms into the pass's norm partials: column c of
+// [A B] sums the thread rows' partials in order; the first window of a
+// one-shot pass stores them (and zeros in the other split slots), later
+// windows and streaming pushes add.
+__global__ __launch_bounds__(256) void fp8_norm_reduce_kernel(const double *__restrict__ nscr, int ny, int nt16,
+                                                              int ntA16, int64_t n1, int64_t ntot, int S,
+                                                              int accumulate, double *__restrict__ npart) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= ntot) return;
+  const int64_t pc = c < n1 ? c : (int64_t)ntA16 * 16 + (c - n1);
+  // four running sums (rows y = 4 i + u go to sum u), added in a fixed order
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  const double *p = nscr + pc;
+  const int64_t stride = (int64_t)nt16 * 16;
+  int y = 0;
+  for (; y + 4 <= ny; y += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s4[u] += p[(int64_t)(y + u) * stride];
+  }
+  for (int u = 0; y < ny; ++y, ++u) s4[u] += p[(int64_t)y * stride];
+  const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  if (accumulate) {
+    npart[c] += s;
+  } else {
+    npart[c] = s;
+    for (int k = 1; k < S; ++k) npart[(int64_t)k * ntot + c] = 0.0;
+  }
+}
+
+// Per 128-row step: each wave loads its two n-tiles' B operands and scale
+// bytes and its share of the chunk's Pi fragments one step ahead; the Pi
+// fragments go through LDS (double buffer), the B operands stay in registers.
+// Steps past the end re-load the last step and multiply zero operands.
+template <int MT>
+__device__ __forceinline__ void loop_fp8_frag(const SkArgs &g, const SkWork &w, int nt0, int ntlast, int i0, int mv,
+                                              v4u8 *L, v4f (&acc)[MT][2]) {
+  constexpr int W = 8, NV = 2;
+  constexpr int CPW = (MT + W - 1) / W;
+  constexpr int LT = CPW * W;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const v4u8 *pi = reinterpret_cast<const v4u8 *>(g.pi) + (int64_t)i0 * kPiUnit8 + 2 * lane;
+  const int64_t fstride = (int64_t)g.mt_total * kPiUnit8;
+  const int64_t blk0 = w.lbeg / KP8;
+  const int64_t nsteps = (w.lend - w.lbeg + KP8 - 1) / KP8;
+  const v4u8 *df = reinterpret_cast<const v4u8 *>(g.dfrag) + lane;   // half h of lane t: unit 64 h + t
+  const uint8_t *ds = g.dscale + lane;
+  int ntv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int t = nt0 + 2 * wave + v;   // past the matrix: its last n-tile (those columns are never stored)
+    ntv[v] = t < ntlast ? t : ntlast;
+  }
+  v4u8 rawb[NV][2];
+  uint32_t raws[NV];
+  v4u8 pst[CPW][2];
+  v8i b[NV];
+  int sb[NV];
+  auto issue = [&](int64_t t) {   // t < nsteps; every load is unconditional
+    const int64_t blk = blk0 + t;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int64_t fb = blk * g.nt16 + ntv[v];
+      rawb[v][0] = df[fb * 128];
+      rawb[v][1] = df[fb * 128 + 64];
+      raws[v] = ds[fb * 64];
+    }
+    const v4u8 *src = pi + blk * fstride;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int i = wave + W * j;
+      const v4u8 *f = src + (i < mv ? i : mv - 1) * kPiUnit8;
+      pst[j][0] = f[0];
+      pst[j][1] = f[1];
+    }
+  };
+  auto land = [&](int64_t t) {   // step t's Pi into LDS buffer t % 2, its B operands into b
+    const bool valid = t < nsteps;
+    v4u8 *Ld = L + (t & 1) * (LT * kPiUnit8);
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int i = wave + W * j;
+      const bool keep = valid && i < mv;
+      Ld[i * kPiUnit8 + 2 * lane] = keep ? pst[j][0] : v4u8{0u, 0u, 0u, 0u};
+      Ld[i * kPiUnit8 + 2 * lane + 1] = keep ? pst[j][1] : v4u8{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const v4u8 lo = valid ? rawb[v][0] : v4u8{0u, 0u, 0u, 0u}, hi = valid ? rawb[v][1] : v4u8{0u, 0u, 0u, 0u};
+      b[v] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      sb[v] = (int)(raws[v] & 0xffu);
+    }
+  };
+  auto frag = [&](const v4u8 *Lc, int i) {
+    const v4u8 lo = Lc[i * kPiUnit8 + 2 * lane], hi = Lc[i * kPiUnit8 + 2 * lane + 1];
+    return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+  };
+  auto multiply = [&](const v4u8 *Lc) {
+    constexpr int G = 2, NG = (MT + G - 1) / G;
+    v8i a[2][G];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < MT) a[0][j] = frag(Lc, j);
+#pragma unroll
+    for (int gr = 0; gr < NG; ++gr) {
+      if (gr + 1 < NG) {
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+          if ((gr + 1) * G + j < MT) a[(gr + 1) & 1][j] = frag(Lc, (gr + 1) * G + j);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int i = gr * G + j;
+        if (i < MT) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            acc[i][v] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[gr & 1][j], b[v], acc[i][v], 0, 0, 0, 127,
+                                                                         0, sb[v]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  issue(0);
+  land(0);
+  for (int64_t t = 0; t < nsteps; ++t) {
+    __syncthreads();   // step t's fragments are in LDS buffer t % 2; buffer (t + 1) % 2 is no longer read
+    issue(t + 1 < nsteps ? t + 1 : nsteps - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    multiply(L + (t & 1) * (LT * kPiUnit8));
+    __builtin_amdgcn_sched_barrier(0);
+    land(t + 1);
+  }
+}
+
+template <int MT>
+__global__ __launch_bounds__(512) void sketch_fp8_frag_kernel(SkArgs g) {
+  constexpr int LT = (MT + 7) / 8 * 8;
+  __shared__ __attribute__((aligned(16))) v4u8 L[2 * LT * kPiUnit8];
+
+  SkWork w;
+  if (!sk_decode(g, w)) return;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int q = lane & 15, gq = lane >> 4;
+  const bool isb = w.col_base != 0;   // B's columns follow A's n1 >= 1 columns
+  const int ntm0 = isb ? g.ntA16 : 0, ntml = isb ? g.nt16 - 1 : g.ntA16 - 1;
+  const int nt0 = ntm0 + w.tile * 16;
+  const int64_t col = (int64_t)w.tile * 256 + wave * 32 + q;   // n-tile v of the wave: columns col + 16 v
+  const int i0 = w.kc * MT;
+  const int mv = g.mt_total - i0 < MT ? g.mt_total - i0 : MT;
+
+  v4f acc[MT][2];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[i][v] = v4f{0.f, 0.f, 0.f, 0.f};
+  const float ksum[2] = {0.f, 0.f}, kcmp[2] = {0.f, 0.f};
+
+  if (w.lbeg < w.lend) loop_fp8_frag<MT>(g, w, nt0, ntml, i0, mv, L, acc);
+  sk_epilogue<MT, 2, 16, false>(g, w, col, i0 * 16, gq, acc, ksum, kcmp);
+}
+
+constexpr int kFragMaxMt8 = 16;
+
+template <int MT>
+struct KTab8F {
+  static void fill(KernelPtr *t) {
+    t[MT] = sketch_fp8_frag_kernel<MT>;
+    KTab8F<MT - 1>::fill(t);
+  }
+};
+template <>
+struct KTab8F<0> {
+  static void fill(KernelPtr *) {}
+};
+
+KernelPtr fp8_frag_kernel_for(int mt) {
+  static KernelPtr t[kFragMaxMt8 + 1];
+  static const bool init = [] {
+    KTab8F<kFragMaxMt8>::fill(t);
+    return true;
+  }();
+  (void)init;
+  return mt >= 1 && mt <= kFragMaxMt8 ? t[mt] : nullptr;
+}
+
+
 template <int NV, int MT>
 struct KTab8 {
   static void fill(KernelPtr *t, KernelPtr *tc, KernelPtr *ts) {
@@ -561,12 +838,45 @@ static SketchPlan sketch_plan_fp8_regen(int k) {
   return p;
 }
 
-// Stored-Pi pass (the default): 128-column tiles (one column per lane), up to
-// 13 m-tiles per workgroup. SMP_SKETCH_FP8_STORED=0 selects the regenerating
-// pass above.
+// Fragment pass (the default): the data quantised window by window into MFMA
+// operands, then 256-column tiles (two n-tiles per wave) of up to 16 m-tiles.
+static SketchPlan sketch_plan_fp8_frag(int k) {
+  SketchPlan p{};
+  p.prec = SMP_PREC_FP8;
+  p.pi_stored = 1;
+  p.frag = 1;
+  p.pi_rows = KP8;
+  p.pi_frag_bytes = kPiUnit8 * 16;
+  p.mt_total = (k + 15) / 16;
+  p.nv = 2;
+  p.waves = 8;
+  p.kc = KP8;
+  p.kt = (p.mt_total + kFragMaxMt8 - 1) / kFragMaxMt8;
+  p.mt = (p.mt_total + p.kt - 1) / p.kt;
+  p.ncol_tile = 16 * 8 * 2;
+  p.kpad = p.mt_total * 16;
+  p.kernel = reinterpret_cast<void *>(fp8_frag_kernel_for(p.mt));
+  p.kernel_clamp = p.kernel;    // the fragment pass has no separate tail launch
+  p.kernel_scalar = p.kernel;   // nor alignment variants (the quantisation reads any layout)
+  return p;
+}
+
+// The stored-Pi pass converts the data in every chunk (128-column tiles, one
+// column per lane, up to 13 m-tiles per workgroup): it reads the FP32 data
+// ceil(k / 208) times, the fragment pass once plus one byte per value per
+// chunk of 256 sketch rows. The fragment pass is the default from three
+// stored-pass chunks (k > 416: 16.5 against 25.2 ms at d = 10^6, n = 8,192,
+// k = 1,024), the stored-Pi pass below (1.31 against 1.35 ms at d = 200,000,
+// n = 4,000, k = 400). SMP_SKETCH_FP8_STORED=0 selects the regenerating pass
+// above, =1 the stored-Pi pass, =2 the fragment pass.
 SketchPlan sketch_plan_fp8(int k) {
-  if (const char *e = getenv("SMP_SKETCH_FP8_STORED"))
+  const int mt_total = (k + 15) / 16;
+  bool frag = mt_total > 2 * kStoredMaxMt8;
+  if (const char *e = getenv("SMP_SKETCH_FP8_STORED")) {
     if (e[0] == '0' && e[1] == 0) return sketch_plan_fp8_regen(k);
+    frag = e[0] == '2' && e[1] == 0;
+  }
+  if (frag) return sketch_plan_fp8_frag(k);
   SketchPlan p{};
   p.prec = SMP_PREC_FP8;
   p.pi_stored = 1;
@@ -584,6 +894,117 @@ SketchPlan sketch_plan_fp8(int k) {
   p.kernel_clamp = reinterpret_cast<void *>(fp8_stored_kernel_for(p.mt, 1));
   p.kernel_scalar = reinterpret_cast<void *>(fp8_stored_kernel_for(p.mt, 2));
   return p;
+}
+
+// ---- fragment pass: the window and its scratch -------------------------------
+// Scratch of one window of wr rows (wr / 128 blocks), each part 256-byte
+// aligned: the Pi fragments (mt_total x 2 KiB per block), the data fragments
+// and scales ((2 KiB + 64 B) per block and n-tile), and the per-thread norm
+// partials (one row of nt16 x 16 FP64 values per 32 x 32 rows). nt16 is
+// bounded by ntot / 16 + 2 (A's and B's n-tiles).
+namespace {
+constexpr int kQuantBlocks32 = 16;   // 32-row blocks per quantising thread
+int64_t frag_nt16_max(const SketchPlan &pl) { return pl.ntot / 16 + 2; }
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+struct FragLayout {
+  size_t pi, data, scale, nscr, total;
+};
+FragLayout frag_layout(const SketchPlan &pl, int64_t wr) {
+  const int64_t nblk = (wr + KP8 - 1) / KP8, nt = frag_nt16_max(pl);
+  const int64_t ny = (4 * nblk + kQuantBlocks32 - 1) / kQuantBlocks32;
+  FragLayout f;
+  f.pi = 0;
+  f.data = al256((size_t)nblk * pl.mt_total * 2048);
+  f.scale = f.data + al256((size_t)nblk * nt * 2048);
+  f.nscr = f.scale + al256((size_t)nblk * nt * 64);
+  f.total = f.nscr + al256((size_t)ny * nt * 16 * 8);
+  return f;
+}
+}  // namespace
+
+int64_t fp8_frag_window_rows(const SketchPlan &pl) {
+  int64_t cap = kFragWindowBytes;
+  if (const char *e = getenv("SMP_PI_WINDOW_MB")) {   // tuning override (as for the Pi windows)
+    const long v = strtol(e, nullptr, 10);
+    if (v >= 1 && v <= 4096) cap = (int64_t)v << 20;
+  }
+  const int64_t nt = frag_nt16_max(pl);
+  const int64_t per_blk = (int64_t)pl.mt_total * 2048 + nt * (2048 + 64) + nt * 16 * 8 * 4 / kQuantBlocks32;
+  return std::max<int64_t>(1, cap / per_blk) * KP8;
+}
+
+size_t fp8_frag_bytes(const SketchPlan &pl, int64_t rows) {
+  if (rows <= 0) return 0;
+  const int64_t wr = std::min<int64_t>((rows + KP8 - 1) / KP8 * KP8, fp8_frag_window_rows(pl));
+  return frag_layout(pl, wr).total;
+}
+
+hipError_t fp8_frag_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
+                         int64_t n2, int64_t rows, int k, uint64_t seed, int64_t row0, int S, bool accumulate,
+                         float *part, double *npart, void *buf, hipStream_t st) {
+  const KernelPtr kern = reinterpret_cast<KernelPtr>(pl.kernel);
+  if (!kern) return hipErrorInvalidValue;
+  if (rows > 0 && !buf) return hipErrorInvalidValue;
+  const int ntA16 = (int)((n1 + 15) / 16), nt16 = ntA16 + (int)((n2 + 15) / 16);
+  if (nt16 > frag_nt16_max(pl)) return hipErrorInvalidValue;   // the scratch was sized for fewer columns
+  const int64_t ntot = n1 + n2;
+  const int64_t wr = fp8_frag_window_rows(pl);
+  const FragLayout lay = frag_layout(pl, std::min<int64_t>((rows + KP8 - 1) / KP8 * KP8, wr));
+  char *cb = static_cast<char *>(buf);
+  SkArgs g{};
+  g.a = SkMat{A, lda, n1, 0, (int)((n1 + pl.ncol_tile - 1) / pl.ncol_tile), 1};
+  g.b = B ? SkMat{B, ldb, n2, n1, (int)((n2 + pl.ncol_tile - 1) / pl.ncol_tile), 1}
+          : SkMat{nullptr, 0, 0, n1, 0, 1};
+  g.ntot = ntot;
+  g.k = k;
+  g.kpad = pl.kpad;
+  g.kt = pl.kt;
+  g.mt_total = pl.mt_total;
+  g.seed = seed;
+  g.part = part;
+  g.npart = npart;
+  g.S = S;
+  g.split_unit = KP8;
+  g.s_base = 0;
+  g.nt16 = nt16;
+  g.ntA16 = ntA16;
+  const int64_t nlog = (int64_t)g.kt * (g.a.ntiles + g.b.ntiles) * S;
+  const unsigned grid = (unsigned)((nlog + 7) / 8 * 8);
+  const int64_t nwin = rows == 0 ? 1 : (rows + wr - 1) / wr;   // a one-shot pass with no rows still stores zeros
+  for (int64_t w = 0; w < nwin; ++w) {
+    const int64_t r0 = w * wr, wrows = std::min<int64_t>(wr, rows - r0);
+    const int nblk = (int)((wrows + KP8 - 1) / KP8);
+    const bool acc = accumulate || w > 0;
+    if (nblk == 0 && accumulate) break;
+    int ny = 0;
+    if (nblk > 0) {
+      hipError_t e = pi_store_fp8(pl, seed, row0 + r0, wrows, k, cb + lay.pi, st);
+      if (e != hipSuccess) return e;
+      QArgs q{A + r0 * lda, B ? B + r0 * ldb : nullptr, lda, ldb, n1, n2, wrows, nblk, nt16, ntA16, kQuantBlocks32,
+              reinterpret_cast<uint8_t *>(cb + lay.data), reinterpret_cast<uint8_t *>(cb + lay.scale),
+              reinterpret_cast<double *>(cb + lay.nscr)};
+      ny = (4 * nblk + kQuantBlocks32 - 1) / kQuantBlocks32;
+      hipLaunchKernelGGL(quantize_fp8_kernel, dim3((unsigned)((nt16 * 16 + 255) / 256), (unsigned)ny), dim3(256), 0,
+                         st, q);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fp8_norm_reduce_kernel, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<const double *>(cb + lay.nscr), ny, nt16, ntA16, n1, ntot, S, acc ? 1 : 0,
+                       npart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    g.row0 = row0 + r0;
+    g.rows = (int64_t)nblk * KP8;
+    g.rows_per_split = (int64_t)(nblk / S) * KP8;
+    g.split_extra = nblk % S;
+    g.accumulate = acc ? 1 : 0;
+    g.pi = cb + lay.pi;
+    g.dfrag = cb + lay.data;
+    g.dscale = reinterpret_cast<const uint8_t *>(cb + lay.scale);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * pl.waves), 0, st, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t pi_store_fp8(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,

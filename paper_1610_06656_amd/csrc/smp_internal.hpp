@@ -54,6 +54,8 @@ struct SketchPlan {
                         // they need (0: nv)
   void *kernel_v2 = nullptr;        // vec_elems > nv: the variants with one nv-wide load per row, for
   void *kernel_v2_clamp = nullptr;  // inputs aligned to nv but not to vec_elems
+  int frag = 0;         // FP8: the data is first quantised, window by window, into MFMA B-operand fragments
+  int64_t ntot = 0;     // frag: n1 + n2 (the columns its fragment windows are sized for)
   int srht = 0;         // 1: the SRHT pass (sketch_srht.hip); mt holds its accumulators per thread
   int64_t d = 0;        // SRHT: rows of A and B (the Hadamard size is the next power of two)
 };
@@ -67,7 +69,7 @@ hipError_t srht_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t 
 
 // Partial-sketch slots a pass with S splits writes: S, plus one for the rows
 // the BF16 / FP8 main launch leaves to its tail launch.
-inline int sketch_slots_total(const SketchPlan &pl, int S) { return pl.prec == SMP_PREC_FP32 ? S : S + 1; }
+inline int sketch_slots_total(const SketchPlan &pl, int S) { return pl.prec == SMP_PREC_FP32 || pl.frag ? S : S + 1; }
 
 // Tile plan for sketch size k and operand precision prec.
 SketchPlan sketch_plan(int k, int prec);
@@ -89,6 +91,18 @@ hipError_t pi_store_bf16(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_
                          hipStream_t st);
 hipError_t pi_store_fp8(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,
                         hipStream_t st);
+
+// FP8 fragment pass (pl.frag): per window of fp8_frag_window_rows(pl) rows the
+// Pi fragments, the data quantised into MFMA B operands with their scales
+// and squared norms, then the GEMM; fp8_frag_bytes(pl, rows) bytes of scratch
+// (at most about kFragWindowBytes, independent of d). Same contract as
+// sketch_push; all S slots are written, there is no tail slot.
+constexpr int64_t kFragWindowBytes = 512ll << 20;
+int64_t fp8_frag_window_rows(const SketchPlan &pl);
+size_t fp8_frag_bytes(const SketchPlan &pl, int64_t rows);
+hipError_t fp8_frag_push(const SketchPlan &pl, const float *A, int64_t lda, int64_t n1, const float *B, int64_t ldb,
+                         int64_t n2, int64_t rows, int k, uint64_t seed, int64_t row0, int S, bool accumulate,
+                         float *part, double *npart, void *buf, hipStream_t st);
 
 // Workgroups of the plan's kernel that the device runs at once
 // (CUs x resident workgroups per CU).

@@ -352,6 +352,70 @@ def test_sketch_fp8_regenerating_pass_parity(api, ctx, name, monkeypatch):
     assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
 
 
+FP8_FRAG_CASES = dict(FP8_CASES, k1024_two_chunks=dict(d=1500, n1=70, n2=300, k=1024),
+                      padded_ld=dict(d=700, n1=45, n2=33, k=500, ld_pad=3))
+
+
+@pytest.mark.parametrize("name", list(FP8_FRAG_CASES))
+def test_sketch_fp8_fragment_pass_parity(api, ctx, name, monkeypatch):
+    """The FP8 pass that first quantises each window of rows into MFMA operand
+    fragments (the default for k > 416; selected here with
+    SMP_SKETCH_FP8_STORED=2 at every k) meets the oracle's FP8 bar: the same
+    E8M0 block scales and E4M3 values, the norms of the unrounded data. Cases
+    cover a single row, a partial last 128-row block (zero-padded), column
+    counts that are not multiples of 16 or 256, two sketch-row chunks and a
+    leading dimension larger than the column count."""
+    monkeypatch.setenv("SMP_SKETCH_FP8_STORED", "2")
+    c = FP8_FRAG_CASES[name]
+    log(f"fp8 fragment sketch {name} {c}")
+    A, B, Ad, Bd = latent(c["d"], c["n1"], c["n2"], R=min(5, c["n1"], c["n2"]))
+    pad = c.get("ld_pad", 0)
+    if pad:   # the same values at a leading dimension of n + pad
+        Ad = torch.zeros(c["d"], c["n1"] + pad, device=DEV)[:, :c["n1"]].copy_(Ad)
+        Bd = torch.zeros(c["d"], c["n2"] + pad, device=DEV)[:, :c["n2"]].copy_(Bd)
+    p = api.make_params(c["d"], c["n1"], c["n2"], c["k"], r=1, prec=api.SMP_PREC_FP8)
+    At, Bt, na2, nb2 = _sketch_gpu(api, ctx, p, Ad, Bd, c["n1"], c["n2"], c["k"])
+    oAt, oBt, ona2, onb2 = osk.sketch_lowp(A.numpy(), B.numpy(), p.seed, c["k"], "fp8")
+    ea, eb = _col_rel(At, oAt), _col_rel(Bt, oBt)
+    log(f"  column rel err A {ea:.2e} B {eb:.2e}")
+    assert ea < TOL_FP8 and eb < TOL_FP8
+    assert np.allclose(na2, ona2, rtol=1e-6, atol=0)
+    assert np.allclose(nb2, onb2, rtol=1e-6, atol=0)
+
+
+def test_sketch_fp8_fragment_pass_windows_and_pushes(api, ctx, monkeypatch):
+    """The fragment pass over many windows (1 MiB: a few 128-row blocks each)
+    and as streaming pushes out of order, starting and ending inside 128-row
+    blocks (whole 32-row blocks only): both meet the oracle's bar and agree
+    with the one-window pass up to the FP32 rounding of the partial sums."""
+    monkeypatch.setenv("SMP_SKETCH_FP8_STORED", "2")
+    d, n1, n2, k = 5000, 130, 70, 640
+    A, B, Ad, Bd = latent(d, n1, n2)
+    oAt, oBt, ona2, onb2 = osk.sketch_lowp(A.numpy(), B.numpy(), SEED, k, "fp8")
+    p = api.make_params(d, n1, n2, k, r=1, prec=api.SMP_PREC_FP8, seed=SEED)
+    outs = []
+    for mb in ("4096", "1"):
+        monkeypatch.setenv("SMP_PI_WINDOW_MB", mb)
+        outs.append(_sketch_gpu(api, ctx, p, Ad, Bd, n1, n2, k))
+    st = ctx.smp_sketch_begin(p)
+    for l0, l1 in [(2080, 5000), (0, 32), (32, 2080)]:
+        ctx.smp_sketch_push(st, Ad[l0:l1], Bd[l0:l1], l0)
+    At = torch.empty(n1, k, device=DEV)
+    Bt = torch.empty(n2, k, device=DEV)
+    na2 = torch.empty(n1, device=DEV)
+    nb2 = torch.empty(n2, device=DEV)
+    ctx.smp_sketch_end(st, At, Bt, na2, nb2)
+    torch.cuda.synchronize()
+    ctx.smp_sketch_free(st)
+    outs.append((At.cpu().numpy(), Bt.cpu().numpy(), na2.cpu().numpy(), nb2.cpu().numpy()))
+    for Ao, Bo, na, nb in outs:
+        assert _col_rel(Ao, oAt) < TOL_FP8 and _col_rel(Bo, oBt) < TOL_FP8
+        assert np.allclose(na, ona2, rtol=1e-6, atol=0) and np.allclose(nb, onb2, rtol=1e-6, atol=0)
+    for Ao, Bo, _, _ in outs[1:]:
+        assert _col_rel(Ao, outs[0][0].T.astype(np.float64)) < 1e-6
+        assert _col_rel(Bo, outs[0][1].T.astype(np.float64)) < 1e-6
+
+
 def test_sketch_fp8_streaming_push_on_block_boundaries(api, ctx):
     d, n1, n2, k = 3000, 130, 70, 64
     A, B, Ad, Bd = latent(d, n1, n2)
