@@ -549,30 +549,34 @@ __global__ __launch_bounds__(256) void quantize_fp8_kernel(QArgs a) {
 }
 
 // The window's squared norms into the pass's norm partials: column c of
-// [A B] sums the thread rows' partials in order; the first window of a
-// one-shot pass stores them (and zeros in the other split slots), later
-// windows and streaming pushes add.
+// [A B] sums the quantising threads' partials (one per 128-row block): 16
+// threads per column each sum every 16th partial in order, and the 16 sums
+// are added in a fixed order (deterministic). The first window of a one-shot
+// pass stores the result (and zeros in the other split slots), later windows
+// and streaming pushes add.
+constexpr int kNormSlices = 16;
 __global__ __launch_bounds__(256) void fp8_norm_reduce_kernel(const double *__restrict__ nscr, int ny, int nt16,
                                                               int ntA16, int64_t n1, int64_t ntot, int S,
                                                               int accumulate, double *__restrict__ npart) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= ntot) return;
-  const int64_t pc = c < n1 ? c : (int64_t)ntA16 * 16 + (c - n1);
-  // four running sums (rows y = 4 i + u go to sum u), added in a fixed order
-  double s4[4] = {0.0, 0.0, 0.0, 0.0};
-  const double *p = nscr + pc;
+  __shared__ double part[kNormSlices][256 / kNormSlices];
+  const int cl = threadIdx.x % (256 / kNormSlices), sl = threadIdx.x / (256 / kNormSlices);
+  const int64_t c = (int64_t)blockIdx.x * (256 / kNormSlices) + cl;
+  const bool cv = c < ntot;
+  const int64_t pc = !cv ? 0 : c < n1 ? c : (int64_t)ntA16 * 16 + (c - n1);
   const int64_t stride = (int64_t)nt16 * 16;
-  int y = 0;
-  for (; y + 4 <= ny; y += 4) {
+  double s = 0.0;
+  if (cv)
+    for (int y = sl; y < ny; y += kNormSlices) s += nscr[(int64_t)y * stride + pc];
+  part[sl][cl] = s;
+  __syncthreads();
+  if (sl != 0 || !cv) return;
+  double t = 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s4[u] += p[(int64_t)(y + u) * stride];
-  }
-  for (int u = 0; y < ny; ++y, ++u) s4[u] += p[(int64_t)y * stride];
-  const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  for (int u = 0; u < kNormSlices; ++u) t += part[u][cl];
   if (accumulate) {
-    npart[c] += s;
+    npart[c] += t;
   } else {
-    npart[c] = s;
+    npart[c] = t;
     for (int k = 1; k < S; ++k) npart[(int64_t)k * ntot + c] = 0.0;
   }
 }
@@ -903,7 +907,7 @@ SketchPlan sketch_plan_fp8(int k) {
 // partials (one row of nt16 x 16 FP64 values per 32 x 32 rows). nt16 is
 // bounded by ntot / 16 + 2 (A's and B's n-tiles).
 namespace {
-constexpr int kQuantBlocks32 = 16;   // 32-row blocks per quantising thread
+constexpr int kQuantBlocks32 = 4;    // 32-row blocks per quantising thread (one 128-row block)
 int64_t frag_nt16_max(const SketchPlan &pl) { return pl.ntot / 16 + 2; }
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 struct FragLayout {
@@ -988,7 +992,7 @@ hipError_t fp8_frag_push(const SketchPlan &pl, const float *A, int64_t lda, int6
                          st, q);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fp8_norm_reduce_kernel, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(fp8_norm_reduce_kernel, dim3((unsigned)((ntot + 15) / 16)), dim3(256), 0, st,
                        reinterpret_cast<const double *>(cb + lay.nscr), ny, nt16, ntA16, n1, ntot, S, acc ? 1 : 0,
                        npart);
     hipError_t e = hipGetLastError();
