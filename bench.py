@@ -249,8 +249,10 @@ def roofline(leg, prec, traffic_name, kernel):
 KERNELS = {
     "bf16": "BF16 sketch pass: per Pi window pi_store_bf16_kernel then sketch_bf16_stored_kernel "
             "(v_mfma_f32_16x16x32_bf16), then the tail launch, timed together",
-    "fp8": "FP8 sketch pass: per Pi window pi_store_fp8_kernel then sketch_fp8_stored_kernel "
-           "(v_mfma_scale_f32_16x16x128_f8f6f4), then the tail launch, timed together",
+    "fp8": "FP8 sketch pass, fragment form at k > 416: per window pi_store_fp8_kernel, quantize_fp8_kernel "
+           "(the data once into E4M3 operand fragments with E8M0 scales and norms), fp8_norm_reduce_kernel and "
+           "sketch_fp8_frag_kernel (v_mfma_scale_f32_16x16x128_f8f6f4), timed together; at k <= 416 the stored-Pi "
+           "form (pi_store_fp8_kernel, sketch_fp8_stored_kernel, tail launch)",
     "fp32": "sketch_kernel (v_mfma_f32_16x16x4f32, Pi regenerated per tile)",
 }
 

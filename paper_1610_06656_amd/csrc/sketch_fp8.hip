@@ -474,6 +474,8 @@ using KernelPtr = void (*)(SkArgs);
 // byte per value per chunk with 16-byte loads, and its tiles hold 2 n-tiles
 // per wave (256 columns per workgroup) and up to 16 m-tiles.
 
+constexpr int kQuantBlocks32 = 4;    // 32-row blocks per quantising thread (one 128-row block)
+
 struct QArgs {
   const float *A, *B;   // the window's first row (B null: A only)
   int64_t lda, ldb, n1, n2;
@@ -482,7 +484,7 @@ struct QArgs {
   int nt16, ntA16;      // n-tiles in all (A's first, then B's) and A's
   int rq;               // 32-row blocks per thread
   uint8_t *frag;        // [nblk][nt16][2 halves][64 lanes][16 B]
-  uint8_t *scale;       // [nblk][nt16][64 lanes]
+  uint8_t *scale;       // [nblk][nt16][16 columns q][4 32-row blocks g]: the scale of operand lane (q, g)
   double *nscr;         // [gridDim.y][nt16 * 16] squared norms of the thread's rows
 };
 
@@ -491,8 +493,9 @@ struct QArgs {
 // of 128-row block j / 4, i.e. K indices 32 gp + i of the operand: its rows
 // i < 16 are bytes 16 (gp / 2) + i of lane (q, 2 (gp % 2)) (half gp / 2 of
 // the fragment), rows i >= 16 the same bytes of lane (q, 2 (gp % 2) + 1), and
-// its scale is the byte of lane (q, gp). Loads are unconditional (clamped row
-// and column, masked after).
+// its scale is the byte of lane (q, gp), stored at 4 q + gp (a thread covers
+// one 128-row block, so it writes its column's four scales as one word).
+// Loads are unconditional (clamped row and column, masked after).
 __global__ __launch_bounds__(256) void quantize_fp8_kernel(QArgs a) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= (int64_t)a.nt16 * 16) return;
@@ -507,7 +510,9 @@ __global__ __launch_bounds__(256) void quantize_fp8_kernel(QArgs a) {
   const int64_t last = a.rows - 1;
   const int j0 = (int)blockIdx.y * a.rq;
   const int j1 = j0 + a.rq < 4 * a.nblk ? j0 + a.rq : 4 * a.nblk;
+  static_assert(kQuantBlocks32 == 4, "a thread covers one 128-row block");
   double s2 = 0.0;
+  uint32_t sc4 = 0;   // byte gp: the scale of 32-row block gp
   // block j + 1's rows are requested before block j is converted
   float xn[32];
   auto load = [&](int j, float (&x)[32]) {
@@ -543,8 +548,10 @@ __global__ __launch_bounds__(256) void quantize_fp8_kernel(QArgs a) {
     const int g0 = 2 * (gp & 1);
     *reinterpret_cast<v4u8 *>(f + (16 * g0 + q) * 16) = v4u8{wv[0], wv[1], wv[2], wv[3]};
     *reinterpret_cast<v4u8 *>(f + (16 * (g0 + 1) + q) * 16) = v4u8{wv[4], wv[5], wv[6], wv[7]};
-    a.scale[fb * 64 + 16 * gp + q] = (uint8_t)(ex + 127);
+    sc4 |= (uint32_t)(ex + 127) << (8 * gp);
   }
+  if (j0 < j1)
+    *reinterpret_cast<uint32_t *>(a.scale + ((int64_t)(j0 >> 2) * a.nt16 + nt) * 64 + 4 * q) = sc4;
   a.nscr[(int64_t)blockIdx.y * a.nt16 * 16 + c] = s2;
 }
 
@@ -598,7 +605,7 @@ __device__ __forceinline__ void loop_fp8_frag(const SkArgs &g, const SkWork &w, 
   const int64_t blk0 = w.lbeg / KP8;
   const int64_t nsteps = (w.lend - w.lbeg + KP8 - 1) / KP8;
   const v4u8 *df = reinterpret_cast<const v4u8 *>(g.dfrag) + lane;   // half h of lane t: unit 64 h + t
-  const uint8_t *ds = g.dscale + lane;
+  const uint8_t *ds = g.dscale + 4 * (lane & 15) + (lane >> 4);   // lane (q, g): byte 4 q + g
   int ntv[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -907,7 +914,6 @@ SketchPlan sketch_plan_fp8(int k) {
 // partials (one row of nt16 x 16 FP64 values per 32 x 32 rows). nt16 is
 // bounded by ntot / 16 + 2 (A's and B's n-tiles).
 namespace {
-constexpr int kQuantBlocks32 = 4;    // 32-row blocks per quantising thread (one 128-row block)
 int64_t frag_nt16_max(const SketchPlan &pl) { return pl.ntot / 16 + 2; }
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 struct FragLayout {
