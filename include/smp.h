@@ -72,6 +72,9 @@ typedef enum smp_precision {
                                scale per column and block of 32 rows (the smallest with
                                max|x| <= 448 * scale); FP32 accumulate on the block-scaled
                                v_mfma_scale_f32_16x16x128_f8f6f4; norms from the unrounded data.
+                               For k > 416 each window of rows is first quantised once into
+                               operand fragments (library scratch of at most about 512 MiB for
+                               a window's Pi, fragments, scales and norms), then multiplied.
                                Streaming pushes must start on a multiple of 32 rows and hold a
                                multiple of 32 rows unless they end at row d. */
 } smp_precision;
@@ -150,7 +153,8 @@ smp_status smp_workspace_size(const smp_params *p, size_t *bytes);
  * passes draw Pi (already rounded, in the matrix-core operand order) one
  * window of data rows at a time into library scratch of at most 128 MiB
  * (smp_workspace_size does not grow with d through Pi) and multiply that
- * window before drawing the next. */
+ * window before drawing the next; the FP8 pass at k > 416 shares its window
+ * with the quantised data (512 MiB in all). */
 smp_status smp_pi_fill(smp_ctx *ctx, const smp_params *p, int64_t l0, int64_t nrows, float *out);
 
 /* ---- a2+a3: the single pass (Alg. 1 step 2; Section 2 "Step 1") -------------
