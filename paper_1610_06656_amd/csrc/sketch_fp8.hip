@@ -462,17 +462,18 @@ __global__ __launch_bounds__(512) void sketch_fp8_stored_kernel(SkArgs g) {
 using KernelPtr = void (*)(SkArgs);
 
 // ---------------------------------------------------------------------------
-// Fragment pass (the default). The stored-Pi pass above reads the FP32 data
-// once per sketch-row chunk (4 bytes per value each time) and converts it in
-// every chunk; here each window of rows is first quantised once, by a
-// streaming kernel, into the B operands of v_mfma_scale_f32_16x16x128_f8f6f4
-// (E4M3 bytes in the operand's lane order, 2 KiB per 128-row block and
-// 16-column n-tile, stored as two 1 KiB halves: bytes 0-15 of every lane,
-// then bytes 16-31, so that the quantiser writes whole lines and the GEMM
-// reads 1 KiB per load instruction) with their E8M0 scales (the same per column and 32-row
-// block as above) and the columns' squared norms; the GEMM then reads one
-// byte per value per chunk with 16-byte loads, and its tiles hold 2 n-tiles
-// per wave (256 columns per workgroup) and up to 16 m-tiles.
+// Fragment pass (the default for k > 416). The stored-Pi pass above reads the
+// FP32 data once per sketch-row chunk (4 bytes per value each time) and
+// converts it in every chunk; here each window of rows is first quantised
+// once, by a streaming kernel, into the B operands of
+// v_mfma_scale_f32_16x16x128_f8f6f4: E4M3 bytes in the operand's lane order,
+// 2 KiB per 128-row block and 16-column n-tile, stored as two 1 KiB halves
+// (bytes 0-15 of every lane, then bytes 16-31) so that the quantiser writes
+// whole lines and the GEMM reads 1 KiB per load instruction; with them the
+// E8M0 scales (the same per column and 32-row block as above) and the
+// columns' squared norms. The GEMM then reads one byte per value per chunk,
+// and its tiles hold 2 n-tiles per wave (256 columns per workgroup) and up to
+// 16 m-tiles.
 
 constexpr int kQuantBlocks32 = 4;    // 32-row blocks per quantising thread (one 128-row block)
 
