@@ -96,9 +96,11 @@ def test_valid_params_and_workspace(lib):
 @pytest.mark.parametrize("prec", [1, 2])
 def test_workspace_does_not_grow_with_d_through_pi(lib, prec):
     """Alg. 1 step 2 draws Pi, the pass does not keep it: the stored-Pi BF16
-    and FP8 passes hold one bounded window of Pi (at most 128 MiB), so
-    from d = 10^6 to d = 10^7 the workspace grows only by what depends on d
-    through the split-K partials and nothing else (it is the same here)."""
+    pass holds one bounded window of Pi (at most 128 MiB) and the FP8
+    fragment pass one window of Pi and data fragments (at most about
+    512 MiB), so from d = 10^6 to d = 10^7 the workspace grows only by what
+    depends on d through the split-K partials and nothing else (it is the
+    same here)."""
     size = ctypes.c_size_t(0)
     sizes = []
     for d in (1_000_000, 4_000_000, 10_000_000):
