@@ -416,6 +416,42 @@ def test_sketch_fp8_fragment_pass_windows_and_pushes(api, ctx, monkeypatch):
         assert _col_rel(Bo, outs[0][1].T.astype(np.float64)) < 1e-6
 
 
+def test_sketch_fp8_fragment_pass_b_is_a(api, ctx, monkeypatch):
+    """The fragment pass for B = A (the PCA case): only A's n-tiles are
+    quantised (no B matrix), one-shot and as out-of-order streaming pushes,
+    with a column count that is not a multiple of 16 and a partial last
+    128-row block; the sketch meets the oracle's FP8 bar and B~ = A~."""
+    monkeypatch.setenv("SMP_SKETCH_FP8_STORED", "2")
+    d, n, k = 1500, 150, 640
+    A, _, Ad, _ = latent(d, n, n, same=True)
+    p = api.make_params(d, n, n, k, r=1, prec=api.SMP_PREC_FP8, b_is_a=True)
+    oAt, _, ona2, _ = osk.sketch_lowp(A.numpy(), None, p.seed, k, "fp8")
+    log(f"fp8 fragment sketch B = A d={d} n={n} k={k}")
+    outs = []
+    for mode in ("one-shot", "pushes"):
+        At = torch.empty(n, k, device=DEV)
+        Bt = torch.empty(n, k, device=DEV)
+        na2 = torch.empty(n, device=DEV)
+        nb2 = torch.empty(n, device=DEV)
+        if mode == "one-shot":
+            ctx.smp_sketch(p, Ad, None, At, Bt, na2, nb2)
+        else:
+            st = ctx.smp_sketch_begin(p)
+            for l0, l1 in [(640, 1500), (0, 64), (64, 640)]:
+                ctx.smp_sketch_push(st, Ad[l0:l1], None, l0)
+            ctx.smp_sketch_end(st, At, Bt, na2, nb2)
+        torch.cuda.synchronize()
+        if mode == "pushes":
+            ctx.smp_sketch_free(st)
+        assert torch.equal(At, Bt) and torch.equal(na2, nb2)
+        e = _col_rel(At.cpu().numpy(), oAt)
+        log(f"  {mode}: column rel err {e:.2e}")
+        assert e < TOL_FP8
+        assert np.allclose(na2.cpu().numpy(), ona2, rtol=1e-6, atol=0)
+        outs.append(At.cpu().numpy())
+    assert _col_rel(outs[1], outs[0].T.astype(np.float64)) < 1e-6
+
+
 def test_sketch_fp8_streaming_push_on_block_boundaries(api, ctx):
     d, n1, n2, k = 3000, 130, 70, 64
     A, B, Ad, Bd = latent(d, n1, n2)
