@@ -340,6 +340,27 @@ smp_status smp_waltmin_group(smp_ctx *ctx, int njobs, const smp_params *p, const
                              const float *const *na2, double *const *U, double *const *V, double *const *sigma,
                              int graph);
 
+/* Sketches of a group of independent BF16 jobs in grouped launches (Alg. 1
+ * step 2 for every job; batching many jobs at once). Job j computes what
+ * smp_sketch(ctx, &p[j], A[j], lda[j], B[j], ldb[j], At[j], Bt[j], na2[j],
+ * nb2[j]) computes, with the same meaning of every argument (SMP_B_IS_A in
+ * p[j].flags: B[j] ignored, Bt[j] and nb2[j] receive copies or may be NULL),
+ * but through the regenerating BF16 pass of its own k: Pi is drawn inside
+ * each tile and never stored, and the jobs whose launches use the same
+ * kernel run as one launch (blockIdx.y = job, each job's arguments from a
+ * device table, each job's work decoded over a grid of its own so that it
+ * still spreads over all XCDs), then one launch for all their tails, then
+ * each job's reduction. Results are the BF16 sketch as the oracle defines it
+ * (the split-K partial sums may be added in another order than smp_sketch's,
+ * so the last FP32 bits can differ). Every p[j].prec must be SMP_PREC_BF16
+ * (else SMP_ERR_INVALID_ARG); njobs <= 65535. Pointers are device pointers
+ * except the arrays themselves and p, which are host arrays of njobs entries
+ * each. The context keeps the jobs' partials and the device job table in its
+ * workspace. Synchronises the stream once (after copying the job table). */
+smp_status smp_sketch_group(smp_ctx *ctx, int njobs, const smp_params *p, const float *const *A,
+                            const int64_t *lda, const float *const *B, const int64_t *ldb, float *const *At,
+                            float *const *Bt, float *const *na2, float *const *nb2);
+
 /* ---- sketch launch-shape tuning (batching and serving) -------------------------
  * The sketch pass has two free launch parameters: the number of row splits
  * (split-K workgroups per column tile) and, for the BF16 stored-Pi pass, the

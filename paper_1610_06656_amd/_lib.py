@@ -87,6 +87,11 @@ EXPORTS = {
     "smp_sketch_push_csr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int64]),
+    "smp_sketch_group": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(SmpParams),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     "smp_waltmin_group": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(SmpParams),
                                          ctypes.POINTER(SmpOmega), ctypes.POINTER(ctypes.c_void_p),
                                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),

@@ -269,6 +269,24 @@ class Context:
                                          _ptr(U, torch.float64, "U"), _ptr(V, torch.float64, "V"),
                                          _ptr(sigma, torch.float64, "sigma")))
 
+    def smp_sketch_group(self, params, As, Bs, Ats, Bts, na2s, nb2s):
+        """smp_sketch for every BF16 job of the lists in grouped launches (B
+        None, or SMP_B_IS_A in the job's flags: B = A; Bt and nb2 may then be
+        None)."""
+        n = len(params)
+        if not (len(As) == len(Bs) == len(Ats) == len(Bts) == len(na2s) == len(nb2s) == n):
+            raise ValueError("job lists differ in length")
+        for X in list(As) + [b for b in Bs if b is not None]:
+            if X.stride(1) != 1:
+                raise ValueError("A and B must have unit column stride")
+        P = (SmpParams * max(1, n))(*params)
+        ptrs = lambda ts, nm, dense=True: (ctypes.c_void_p * max(1, n))(
+            *[_ptr(t, torch.float32, nm, dense=dense) for t in ts])
+        lds = lambda ts: (ctypes.c_int64 * max(1, n))(*[t.stride(0) if t is not None else 0 for t in ts])
+        self._check(self.lib.smp_sketch_group(self.h, n, P, ptrs(As, "A", False), lds(As), ptrs(Bs, "B", False),
+                                              lds(Bs), ptrs(Ats, "At"), ptrs(Bts, "Bt"), ptrs(na2s, "na2"),
+                                              ptrs(nb2s, "nb2")))
+
     def smp_waltmin_group(self, params, omegas, na2s, Us, Vs, sigmas=None, graph=True):
         """smp_waltmin for every job of the lists at once (grouped launches,
         one HIP graph per group of equal launch sequences with graph=True)."""

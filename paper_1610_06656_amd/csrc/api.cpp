@@ -245,7 +245,7 @@ static void *scratch_for(int device) {
 }
 
 struct smp_ctx_bufs {
-  Buf sketch, samplews, head, omega, est, wm, mn, base, sparse, tune, group;
+  Buf sketch, samplews, head, omega, est, wm, mn, base, sparse, tune, group, skgroup;
 };
 
 namespace {
@@ -637,6 +637,38 @@ smp_status smp_sketch_push_csr(smp_ctx *ctx, smp_sketch_state *st, int which, in
   in.vals = vals;
   in.nnz = nnz;
   return push_entries(ctx, st, which, in);
+}
+
+smp_status smp_sketch_group(smp_ctx *ctx, int njobs, const smp_params *p, const float *const *A,
+                            const int64_t *lda, const float *const *B, const int64_t *ldb, float *const *At,
+                            float *const *Bt, float *const *na2, float *const *nb2) {
+  if (!ctx) return fail(nullptr, SMP_ERR_INVALID_ARG, "ctx is NULL");
+  if (njobs < 0 || njobs > 65535) return fail(ctx, SMP_ERR_INVALID_ARG, "njobs outside [0, 65535]");
+  if (njobs == 0) return SMP_OK;
+  if (!p || !A || !lda || !B || !ldb || !At || !Bt || !na2 || !nb2)
+    return fail(ctx, SMP_ERR_INVALID_ARG, "an argument array is NULL");
+  std::vector<smp::GroupSketchJob> jobs(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    const std::string m = check(&p[j]);
+    const std::string pre = "job " + std::to_string(j) + ": ";
+    if (!m.empty()) return fail(ctx, SMP_ERR_INVALID_ARG, pre + m);
+    if (p[j].prec != SMP_PREC_BF16) return fail(ctx, SMP_ERR_INVALID_ARG, pre + "smp_sketch_group runs BF16 jobs only");
+    if (p[j].flags & SMP_SKETCH_SRHT) return fail(ctx, SMP_ERR_INVALID_ARG, pre + "the SRHT sketch is not grouped");
+    const bool same = (p[j].flags & SMP_B_IS_A) != 0;
+    if (!A[j] || lda[j] < p[j].n1) return fail(ctx, SMP_ERR_INVALID_ARG, pre + "A is NULL or lda < n1");
+    if (!same && (!B[j] || ldb[j] < p[j].n2)) return fail(ctx, SMP_ERR_INVALID_ARG, pre + "B is NULL or ldb < n2");
+    if (!At[j] || !na2[j] || (!same && (!Bt[j] || !nb2[j])))
+      return fail(ctx, SMP_ERR_INVALID_ARG, pre + "output pointer is NULL");
+    jobs[j] = smp::GroupSketchJob{A[j], same ? nullptr : B[j], lda[j], same ? 0 : ldb[j], p[j].n1,
+                                  same ? p[j].n1 : p[j].n2, p[j].d, (int)p[j].k, p[j].seed,
+                                  At[j], Bt[j], na2[j], nb2[j]};
+  }
+  const size_t need = smp::bf16_group_scratch_bytes(jobs.data(), njobs);
+  smp_ctx_bufs &b = bufs(ctx);
+  smp_status s = ensure(ctx, b.skgroup, need);
+  if (s != SMP_OK) return s;
+  SMP_HIP(ctx, smp::bf16_sketch_group(jobs.data(), njobs, b.skgroup.p, b.skgroup.bytes, ctx->stream));
+  return SMP_OK;
 }
 
 smp_status smp_sketch(smp_ctx *ctx, const smp_params *p, const float *A, int64_t lda, const float *B, int64_t ldb,

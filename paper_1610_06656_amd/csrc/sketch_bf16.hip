@@ -51,6 +51,8 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
+#include <vector>
 
 #include "sketch_common.hpp"
 #include "smp_device.hpp"
@@ -317,14 +319,12 @@ __device__ __forceinline__ void loop_bf16(const SkArgs &g, const SkWork &w, int6
 // (rows past a split's end are clamped and masked); the main launch of a pass
 // covers whole blocks only and runs without.
 template <int MT, int NV, int W, int GS, bool VEC, bool CLAMP>
-__global__ __launch_bounds__(64 * W) void sketch_bf16_kernel(SkArgs g) {
+__device__ __forceinline__ void sketch_bf16_body(const SkArgs &g, const SkWork &w) {
   constexpr int KP = 16 * W;
   constexpr int PSTW = KP / 2 + 4;
   constexpr int PBUF = MT * 16 * PSTW;   // dwords of one Pi block
   __shared__ __attribute__((aligned(16))) uint32_t P[2 * PBUF];
 
-  SkWork w;
-  if (!sk_decode(g, w)) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int q = lane & 15, gq = lane >> 4;
@@ -348,20 +348,49 @@ __global__ __launch_bounds__(64 * W) void sketch_bf16_kernel(SkArgs g) {
   sk_epilogue<MT, NV>(g, w, col, c0, gq, acc, ksum, kcmp);
 }
 
+template <int MT, int NV, int W, int GS, bool VEC, bool CLAMP>
+__global__ __launch_bounds__(64 * W) void sketch_bf16_kernel(SkArgs g) {
+  SkWork w;
+  if (!sk_decode(g, w)) return;
+  sketch_bf16_body<MT, NV, W, GS, VEC, CLAMP>(g, w);
+}
+
+// Grouped form: the launch of many jobs' passes at once (blockIdx.y = job,
+// its arguments and its own grid size from a device table; grid.x is the
+// largest of the jobs' grids). Workgroup b of a job is its workgroup b of a
+// launch of its own, decoded over the job's grid, so each job's work keeps the
+// XCD spread of a launch of its own; the surplus workgroups of smaller jobs
+// exit at once.
+template <int MT, int NV, int W, int GS, bool VEC, bool CLAMP>
+__global__ __launch_bounds__(64 * W) void sketch_bf16_group_kernel(const SkJob *__restrict__ jobs) {
+  const int grid = jobs[blockIdx.y].grid;
+  if ((int)blockIdx.x >= grid) return;
+  const SkArgs g = jobs[blockIdx.y].g;   // uniform: held in scalar registers like kernel arguments
+  SkWork w;
+  if (!sk_decode_in(g, w, (int)blockIdx.x, grid)) return;
+  sketch_bf16_body<MT, NV, W, GS, VEC, CLAMP>(g, w);
+}
+
 using KernelPtr = void (*)(SkArgs);
+
+using GroupKernelPtr = void (*)(const SkJob *);
 
 template <int NV, int W, int GS, int MT>
 struct KTab {
-  static void fill(KernelPtr *t, KernelPtr *tc, KernelPtr *ts) {
+  static void fill(KernelPtr *t, KernelPtr *tc, KernelPtr *ts, GroupKernelPtr *gt, GroupKernelPtr *gtc,
+                   GroupKernelPtr *gts) {
     t[MT] = sketch_bf16_kernel<MT, NV, W, GS, true, false>;
     tc[MT] = sketch_bf16_kernel<MT, NV, W, GS, true, true>;
     ts[MT] = sketch_bf16_kernel<MT, NV, W, GS, false, true>;
-    KTab<NV, W, GS, MT - 1>::fill(t, tc, ts);
+    gt[MT] = sketch_bf16_group_kernel<MT, NV, W, GS, true, false>;
+    gtc[MT] = sketch_bf16_group_kernel<MT, NV, W, GS, true, true>;
+    gts[MT] = sketch_bf16_group_kernel<MT, NV, W, GS, false, true>;
+    KTab<NV, W, GS, MT - 1>::fill(t, tc, ts, gt, gtc, gts);
   }
 };
 template <int NV, int W, int GS>
 struct KTab<NV, W, GS, 0> {
-  static void fill(KernelPtr *, KernelPtr *, KernelPtr *) {}
+  static void fill(KernelPtr *, KernelPtr *, KernelPtr *, GroupKernelPtr *, GroupKernelPtr *, GroupKernelPtr *) {}
 };
 
 // gs: the K steps of a block over which the next block's Pi generation is
@@ -371,17 +400,18 @@ struct Shape {
   KernelPtr t[14];    // vector loads, whole blocks
   KernelPtr tc[14];   // vector loads, clamped partial blocks
   KernelPtr ts[14];   // guarded scalar loads, clamped
+  GroupKernelPtr gt[14], gtc[14], gts[14];   // the same three as grouped launches
 };
 
 Shape *shapes(int &count) {
   // (nv, waves, largest mt that keeps the kernel in registers without scratch)
   // the largest mt of each shape is the largest whose main kernel stays in
   // registers (no scratch) at two waves per SIMD
-  static Shape tabs[] = {{4, 8, 4, 4, {}, {}, {}}, {2, 8, 4, 12, {}, {}, {}}};
+  static Shape tabs[] = {{4, 8, 4, 4, {}, {}, {}, {}, {}, {}}, {2, 8, 4, 12, {}, {}, {}, {}, {}, {}}};
   // function-local statics initialise once, also under concurrent first calls
   static const bool init = [] {
-    KTab<4, 8, 4, 4>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts);
-    KTab<2, 8, 4, 12>::fill(tabs[1].t, tabs[1].tc, tabs[1].ts);
+    KTab<4, 8, 4, 4>::fill(tabs[0].t, tabs[0].tc, tabs[0].ts, tabs[0].gt, tabs[0].gtc, tabs[0].gts);
+    KTab<2, 8, 4, 12>::fill(tabs[1].t, tabs[1].tc, tabs[1].ts, tabs[1].gt, tabs[1].gtc, tabs[1].gts);
     return true;
   }();
   (void)init;
@@ -396,6 +426,16 @@ KernelPtr bf16_kernel_for(int nv, int mt, int waves, int gs, int variant) {
   for (int i = 0; i < count; ++i)
     if (t[i].nv == nv && t[i].waves == waves && t[i].gs == gs && mt >= 1 && mt <= t[i].max_mt)
       return variant == 0 ? t[i].t[mt] : variant == 1 ? t[i].tc[mt] : t[i].ts[mt];
+  return nullptr;
+}
+
+// the grouped kernel of the same shape and variant as a plan's kernel
+GroupKernelPtr bf16_group_kernel_for(int nv, int mt, int waves, int gs, int variant) {
+  int count = 0;
+  Shape *t = shapes(count);
+  for (int i = 0; i < count; ++i)
+    if (t[i].nv == nv && t[i].waves == waves && t[i].gs == gs && mt >= 1 && mt <= t[i].max_mt)
+      return variant == 0 ? t[i].gt[mt] : variant == 1 ? t[i].gtc[mt] : t[i].gts[mt];
   return nullptr;
 }
 
@@ -813,6 +853,154 @@ SketchPlan sketch_plan_bf16(int k, int cap_in) {
     p.kernel_v2_clamp = reinterpret_cast<void *>(bf16_stored_kernel_for(nv, waves, depth, p.mt, 4));
   }
   return p;
+}
+
+// ---- grouped sketch of many jobs ---------------------------------------------
+// Each job: its own regenerating BF16 plan, S splits of at least 64 whole
+// blocks each (at most 16), a main launch over the whole blocks and a tail
+// launch (one split, clamped) over the rest into partial slot S, exactly as a
+// pass of its own would run them; the grouping only puts the jobs whose
+// launches use the same kernel into one launch.
+namespace {
+struct GroupJobShape {
+  SketchPlan pl;
+  int S;
+  int64_t n2e;   // B's columns in the pass (0 for B = A)
+  size_t part_bytes, npart_bytes;
+};
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+GroupJobShape group_job_shape(const GroupSketchJob &j) {
+  GroupJobShape s;
+  s.pl = sketch_plan_bf16_regen(j.k);
+  const int64_t nblk = j.d / s.pl.kc;
+  s.S = (int)std::max<int64_t>(1, std::min<int64_t>(16, nblk / 64));
+  s.n2e = j.B ? j.n2 : 0;
+  const int64_t nt = j.n1 + s.n2e;
+  s.part_bytes = al256((size_t)(s.S + 1) * nt * s.pl.kpad * 4);
+  s.npart_bytes = al256((size_t)(s.S + 1) * nt * 8);
+  return s;
+}
+}  // namespace
+
+size_t bf16_group_scratch_bytes(const GroupSketchJob *jobs, int njobs) {
+  size_t b = al256((size_t)2 * std::max(njobs, 1) * sizeof(SkJob));
+  for (int i = 0; i < njobs; ++i) {
+    const GroupJobShape s = group_job_shape(jobs[i]);
+    b += s.part_bytes + s.npart_bytes;
+  }
+  return b;
+}
+
+hipError_t bf16_sketch_group(const GroupSketchJob *jobs, int njobs, void *scratch, size_t scratch_bytes,
+                             hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  if (njobs > 65535 || !scratch || scratch_bytes < bf16_group_scratch_bytes(jobs, njobs)) return hipErrorInvalidValue;
+  char *cb = static_cast<char *>(scratch);
+  SkJob *dtab = reinterpret_cast<SkJob *>(cb);
+  size_t off = al256((size_t)2 * njobs * sizeof(SkJob));
+  auto aligned = [](const float *X, int64_t ld, int64_t n, int e) {
+    const int vb = 4 * e;
+    return ld % e == 0 && n % e == 0 && ((uintptr_t)X % (vb > 16 ? 16 : vb)) == 0;
+  };
+  std::vector<SkJob> tab(2 * (size_t)njobs);   // main launches, then tail launches
+  std::vector<GroupKernelPtr> kern(2 * (size_t)njobs);
+  std::vector<GroupJobShape> shape(njobs);
+  std::vector<float *> parts(njobs);
+  std::vector<double *> nparts(njobs);
+  for (int i = 0; i < njobs; ++i) {
+    const GroupSketchJob &j = jobs[i];
+    const GroupJobShape sh = group_job_shape(j);
+    shape[i] = sh;
+    const SketchPlan &pl = sh.pl;
+    parts[i] = reinterpret_cast<float *>(cb + off);
+    nparts[i] = reinterpret_cast<double *>(cb + off + sh.part_bytes);
+    off += sh.part_bytes + sh.npart_bytes;
+    const int nct = pl.ncol_tile;
+    SkArgs g{};
+    g.a = SkMat{j.A, j.lda, j.n1, 0, (int)((j.n1 + nct - 1) / nct), (int)aligned(j.A, j.lda, j.n1, pl.nv)};
+    g.b = j.B ? SkMat{j.B, j.ldb, j.n2, j.n1, (int)((j.n2 + nct - 1) / nct), (int)aligned(j.B, j.ldb, j.n2, pl.nv)}
+              : SkMat{nullptr, 0, 0, j.n1, 0, 1};
+    g.ntot = j.n1 + sh.n2e;
+    g.k = j.k;
+    g.kpad = pl.kpad;
+    g.kt = pl.kt;
+    g.mt_total = pl.mt_total;
+    g.accumulate = 0;
+    g.seed = j.seed;
+    g.part = parts[i];
+    g.npart = nparts[i];
+    const bool vec = g.a.vec_ok && g.b.vec_ok;
+    const int64_t nblk = j.d / pl.kc, main_rows = nblk * pl.kc, tail = j.d - main_rows;
+    // main launch: the whole blocks over S splits (with no whole block it still stores zero partials)
+    SkJob m{g, 0};
+    m.g.row0 = 0;
+    m.g.rows = main_rows;
+    m.g.S = sh.S;
+    m.g.rows_per_split = nblk / sh.S * pl.kc;
+    m.g.split_extra = (int)(nblk % sh.S);
+    m.g.split_unit = pl.kc;
+    m.g.s_base = 0;
+    m.grid = (int)(((int64_t)pl.kt * (g.a.ntiles + g.b.ntiles) * sh.S + 7) / 8 * 8);
+    // tail launch: the rows past the last whole block, one split, into slot S
+    SkJob t{g, 0};
+    t.g.row0 = main_rows;
+    t.g.rows = tail;
+    t.g.S = 1;
+    t.g.rows_per_split = (tail + pl.kc - 1) / pl.kc * pl.kc;
+    t.g.split_extra = 0;
+    t.g.split_unit = 0;
+    t.g.s_base = sh.S;
+    t.g.a.X = j.A + main_rows * j.lda;
+    if (j.B) t.g.b.X = j.B + main_rows * j.ldb;
+    t.grid = (int)(((int64_t)pl.kt * (g.a.ntiles + g.b.ntiles) + 7) / 8 * 8);
+    kern[i] = bf16_group_kernel_for(pl.nv, pl.mt, pl.waves, 4, vec ? 0 : 2);
+    kern[njobs + i] = bf16_group_kernel_for(pl.nv, pl.mt, pl.waves, 4, vec ? 1 : 2);
+    if (!kern[i] || !kern[njobs + i] || pl.waves != 8) return hipErrorInvalidValue;
+    tab[i] = m;
+    tab[njobs + i] = t;
+  }
+  // order each half of the table by kernel, so that a launch's jobs are contiguous
+  std::vector<int> order(2 * (size_t)njobs);
+  for (int i = 0; i < 2 * njobs; ++i) order[i] = i;
+  auto by_kernel = [&](int a, int b) {
+    const bool ta = a >= njobs, tb = b >= njobs;
+    if (ta != tb) return tb;   // main launches first
+    if (kern[a] != kern[b]) return std::less<const void *>()(reinterpret_cast<const void *>(kern[a]),
+                                                            reinterpret_cast<const void *>(kern[b]));
+    return a < b;
+  };
+  std::sort(order.begin(), order.end(), by_kernel);
+  std::vector<SkJob> sorted(2 * (size_t)njobs);
+  for (int i = 0; i < 2 * njobs; ++i) sorted[i] = tab[order[i]];
+  hipError_t e = hipMemcpyAsync(dtab, sorted.data(), sorted.size() * sizeof(SkJob), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;   // the host table is freed on return
+  for (int i0 = 0; i0 < 2 * njobs;) {
+    int i1 = i0 + 1;
+    while (i1 < 2 * njobs && (order[i1] >= njobs) == (order[i0] >= njobs) && kern[order[i1]] == kern[order[i0]]) ++i1;
+    int gx = 8;
+    for (int i = i0; i < i1; ++i) gx = std::max(gx, sorted[i].grid);
+    hipLaunchKernelGGL(kern[order[i0]], dim3((unsigned)gx, (unsigned)(i1 - i0)), dim3(64 * 8), 0, st,
+                       static_cast<const SkJob *>(dtab + i0));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    i0 = i1;
+  }
+  for (int i = 0; i < njobs; ++i) {
+    const GroupSketchJob &j = jobs[i];
+    const GroupJobShape &sh = shape[i];
+    if ((e = sketch_finish(sh.pl, parts[i], nparts[i], sh.S + 1, j.n1, sh.n2e, j.k, j.At, j.B ? j.Bt : nullptr,
+                           j.na2, j.B ? j.nb2 : nullptr, st)) != hipSuccess)
+      return e;
+    if (!j.B) {
+      if (j.Bt && j.Bt != j.At &&
+          (e = hipMemcpyAsync(j.Bt, j.At, (size_t)j.n1 * j.k * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return e;
+      if (j.nb2 && j.nb2 != j.na2 &&
+          (e = hipMemcpyAsync(j.nb2, j.na2, (size_t)j.n1 * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return e;
+    }
+  }
+  return hipSuccess;
 }
 
 hipError_t pi_store_bf16(const SketchPlan &pl, uint64_t seed, int64_t r0, int64_t rows, int k, void *buf,

@@ -52,10 +52,10 @@ struct SkWork {
 // logical id keeps consecutive ids on one XCD, and the kt workgroups that
 // read the same data tile (same column tile and split, different sketch-row
 // chunk) have consecutive logical ids, so their reads of that tile meet in the
-// XCD's L2. Returns false for the padding workgroups.
-__device__ __forceinline__ bool sk_decode(const SkArgs &g, SkWork &w) {
-  const int nb = gridDim.x;
-  const int b = blockIdx.x;
+// XCD's L2. Returns false for the padding workgroups. sk_decode_in decodes
+// workgroup b of a grid of nb (a multiple of 8) given explicitly (a job of a
+// grouped launch), sk_decode the launch's own.
+__device__ __forceinline__ bool sk_decode_in(const SkArgs &g, SkWork &w, int b, int nb) {
   const int logical = (b & 7) * (nb >> 3) + (b >> 3);
   const int ntl = g.a.ntiles + g.b.ntiles;
   if (logical >= g.kt * ntl * g.S) return false;
@@ -78,6 +78,17 @@ __device__ __forceinline__ bool sk_decode(const SkArgs &g, SkWork &w) {
   w.lend = w.lbeg + span < g.rows ? w.lbeg + span : g.rows;
   return true;
 }
+
+__device__ __forceinline__ bool sk_decode(const SkArgs &g, SkWork &w) {
+  return sk_decode_in(g, w, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// One job of a grouped launch: its arguments and the grid of a launch of its
+// own (a multiple of 8).
+struct SkJob {
+  SkArgs g;
+  int grid;
+};
 
 // NV adjacent columns of one data row into registers. FULL: the whole tile is
 // inside the matrix and the vector loads are aligned, so the load is

@@ -124,6 +124,24 @@ hipError_t sketch_finish(const SketchPlan &pl, const float *part, const double *
 
 hipError_t pi_fill(int64_t l0, int64_t nrows, int k, uint64_t seed, float *out, hipStream_t st);
 
+// Grouped BF16 sketch of many independent jobs (each the whole pass of its own
+// d x n1 A and d x n2 B; B null: B = A, n2 is then A's). Every job runs the
+// regenerating BF16 pass of its own k (Pi drawn inside each tile, never
+// stored); the main launches of all jobs with the same kernel go out as one
+// launch, then their tail launches, then each job's finish. scratch holds the
+// jobs' split-K partials and the device job table:
+// bf16_group_scratch_bytes(jobs, n) bytes.
+struct GroupSketchJob {
+  const float *A, *B;
+  int64_t lda, ldb, n1, n2, d;
+  int k;
+  uint64_t seed;
+  float *At, *Bt, *na2, *nb2;   // Bt and nb2 receive copies of At and na2 when B = A (may be null then)
+};
+size_t bf16_group_scratch_bytes(const GroupSketchJob *jobs, int njobs);
+hipError_t bf16_sketch_group(const GroupSketchJob *jobs, int njobs, void *scratch, size_t scratch_bytes,
+                             hipStream_t st);
+
 // ---- sampling ------------------------------------------------------------------
 struct SampleWs {
   double *stats;     // [8]: F_A, F_B, den_A, den_B, non-finite flag (1.0 when F_A or F_B is not finite)
