@@ -345,6 +345,52 @@ def run_batch_group(api, jobs, pools, prec, workers, graph=True):
             "graph": bool(graph)}
 
 
+def run_sketch_group(api, jobs, pools):
+    """The BF16 sketches alone of the batching mix's jobs: one smp_sketch per
+    job on one context (the stored-Pi pass) against smp_sketch_group over all
+    of them (the regenerating pass, jobs with the same kernel in one launch).
+    Median of three timed runs after one warm-up each."""
+    import torch
+    dev = pools[0][0].device
+    ctx = api.Context(0)
+    P, As, Bs, outs, byts = [], [], [], [], 0.0
+    for j in jobs:
+        A, B = pools[j["pool"]]
+        d, n, k = j["d"], j["n"], j["k"]
+        P.append(api.make_params(d, n, n, k, j["r"], seed=j["seed"], prec=api.SMP_PREC_BF16))
+        As.append(A[:d, :n])
+        Bs.append(B[:d, :n])
+        outs.append((torch.empty(n, k, device=dev), torch.empty(n, k, device=dev), torch.empty(n, device=dev),
+                     torch.empty(n, device=dev)))
+        byts += 8.0 * d * n
+
+    def each():
+        for p, A, B, o in zip(P, As, Bs, outs):
+            ctx.smp_sketch(p, A, B, *o)
+
+    def group():
+        ctx.smp_sketch_group(P, As, Bs, *[[o[i] for o in outs] for i in range(4)])
+
+    res = {}
+    for name, f in (("per_job_ms", each), ("grouped_ms", group)):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        res[name] = round(sorted(ts)[1] * 1e3, 2)
+    del outs
+    torch.cuda.empty_cache()
+    res["per_job_gbps"] = round(byts / res["per_job_ms"] / 1e6, 1)
+    res["grouped_gbps"] = round(byts / res["grouped_ms"] / 1e6, 1)
+    res["what"] = ("the BF16 sketches alone of the batch jobs: one smp_sketch per job (stored-Pi pass) against one "
+                   "smp_sketch_group call (regenerating pass, grouped launches)")
+    return res
+
+
 def mix_legs(api, args, pools, large_pool, dev):
     """The batching mix (512 jobs at once) and the serving mix (Poisson
     arrivals, 5% large jobs), each with BF16 and FP32 sketches."""
@@ -376,6 +422,7 @@ def mix_legs(api, args, pools, large_pool, dev):
             for leg, prec in (("bf16", api.SMP_PREC_BF16), ("fp32", api.SMP_PREC_FP32)):
                 run_batch_group(api, jobs[:8], pools, prec, args.workers)          # warm-up
                 legs["group_" + leg] = run_batch_group(api, jobs, pools, prec, args.workers)
+            legs["sketch_group"] = run_sketch_group(api, jobs, pools)
         out[name] = legs
     out["batch"]["workload"] = (f"{b['jobs']} independent jobs submitted at once: d uniform in [10k, 200k], n1 = n2 "
                                 f"uniform in [128, 2048], r in {{5, 10, 20}}, k = r * uniform{{4..20}}, T = 10, "
